@@ -1,0 +1,21 @@
+"""CPU oracle for the lambda-leveling loop (test infrastructure only).
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product library never calls it, and the two share no
+code: the oracle computes every connectivity number by flood fill over the
+8-ring (``thin_oracle.c``), the product from its own tables.
+"""
+from .oracle import (  # noqa: F401
+    ADJ_8_4,
+    ADJ_4_8,
+    OracleError,
+    build,
+    classify,
+    classify_patch,
+    count_destructible,
+    queue,
+    ring_offsets,
+    sweep,
+    sweep_dirty,
+    sweep_ordered,
+)
