@@ -1,0 +1,301 @@
+#!/usr/bin/env python3
+"""Throughput of the lambda-leveling loop on one MI355X.
+
+Default workload (one JSON line): a single 512x512 u8 ridge image (Gaussian-
+filtered noise with 20 bright 1-pixel polylines), lambda = 20, (8,4), thinned
+to stability by the plain per-image path.  A "step" is one full run of the
+loop on one image: every parity step until a pass without lowering.  Inputs
+are staged in HBM before the timed region (one copy per step, because the
+library works in place); the timed region brackets exactly --steps runs with
+a device synchronisation on both sides.
+
+Other workloads (--workload): blobs_128, blobs_8192_u16, batch_512 (512
+uneven images in one batched call, compared with 512 plain calls).
+
+The JSON line carries:
+  value      Mpixel/s (pixels of input images thinned to stability per second)
+  roofline   streaming-equivalent HBM rate of the round kernel: the algorithmic
+             bytes 2*b*H*W*P of a run (b bytes per pixel, P passes) divided by
+             the summed duration of its round-kernel launches (HIP events on
+             the library's stream), against 8 TB/s
+  cpu_baseline  the CPU oracle (single-thread C, dirty-pixel sweep) on the
+             same image(s), as a reported baseline
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("Mpixel/s and images/s to convergence (bit-exact), batched vs plain; "
+          "p50/p99 latency")
+HBM_PEAK_GBS = 8000.0
+
+
+def _percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def _ensure_built():
+    from paper_1603_09180_amd import thin
+    if not os.path.exists(thin.LIB_PATH):
+        from paper_1603_09180_amd import build
+        build.build()
+    import oracle
+    oracle.build(force=False)
+
+
+def _traffic_for(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if one
+    exists for this kernel source; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    from paper_1603_09180_amd import build
+    if rec.get("source_digest") != build.source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(images, budget_s: float):
+    """Times the oracle's dirty-pixel sweep (single thread) on the images, in
+    order, repeating until about budget_s seconds of CPU work."""
+    import oracle
+    t0 = time.perf_counter()
+    px = 0
+    n = 0
+    while True:
+        for F, lam, adj in images:
+            oracle.sweep_dirty(F, lam, adj)
+            px += F.shape[0] * F.shape[1]
+            n += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return px / dt / 1e6, n, dt
+
+
+def bench_single(job, name, steps, warmup, cpu_s, tile, k):
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1603_09180_amd import thin
+
+    F = job.image()
+    h, w = F.shape
+    b = F.dtype.itemsize
+    ref = oracle.sweep_dirty(F, job.lam, job.adj)
+    src = torch.from_numpy(F).cuda()
+    inputs = [src.clone() for _ in range(warmup + steps)]
+    torch.cuda.synchronize()
+    ctx = thin.Context(device=0, profile=True, tile=tile, steps_per_round=k)
+    for i in range(warmup):
+        ctx.run(inputs[i], job.lam, job.adj)
+    torch.cuda.synchronize()
+    got = inputs[0].cpu().numpy()
+    bit_exact = bool(np.array_equal(got, ref.image))
+    ctx.profile(reset=True)
+    lat = []
+    stats = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        s0 = time.perf_counter()
+        stats = ctx.run(inputs[warmup + i], job.lam, job.adj)
+        lat.append((time.perf_counter() - s0) * 1e3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile(reset=True)
+    ctx.close()
+    last = inputs[warmup + steps - 1].cpu().numpy()
+    bit_exact = bit_exact and bool(np.array_equal(last, ref.image))
+    bit_exact = bit_exact and (stats.passes, stats.lowerings) == (ref.passes, ref.lowerings)
+
+    elapsed = t1 - t0
+    mpx = h * w * steps / elapsed / 1e6
+    alg_bytes = 2 * b * h * w * ref.passes * steps
+    launches = max(int(prof.launches), 1)
+    kernel_s = prof.kernel_ms / 1e3
+    achieved = alg_bytes / kernel_s / 1e9 if kernel_s > 0 else None
+    traffic = _traffic_for("k_round", name)
+    out = {
+        "metric": METRIC,
+        "value": round(mpx, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": round(elapsed / steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8" if b == 1 else "u16",
+        "data": "synthetic",
+        "config": {"workload": name, "h": h, "w": w, "lambda": job.lam,
+                   "adjacency": "8,4" if job.adj == 0 else "4,8", "images_per_step": 1,
+                   "path": "plain (thin_run)"},
+        "images_per_s": round(steps / elapsed, 2),
+        "latency_ms_p50": round(_percentile(lat, 0.5), 4),
+        "latency_ms_p99": round(_percentile(lat, 0.99), 4),
+        "passes": int(stats.passes),
+        "lowerings": int(stats.lowerings),
+        "bit_exact": bit_exact,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_round",
+            "achieved": round(achieved, 2) if achieved else None,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": traffic,
+            "launches_per_step": round(launches / steps, 2),
+            "avg_launch_us": round(prof.kernel_ms * 1e3 / launches, 3),
+            "alg_bytes_per_launch": round(alg_bytes / launches, 1),
+            "kernel_time_frac_of_step": round(kernel_s / elapsed, 4),
+        },
+    }
+    if cpu_s > 0:
+        v, n, dt = cpu_baseline([(F, job.lam, job.adj)], cpu_s)
+        out["cpu_baseline"] = {"value": round(v, 4), "unit": "Mpixel/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"ORACLE-SWEEP-DIRTY, single-thread C, {n} run(s) of the "
+                                         f"same {h}x{w} image in {dt:.1f} s"}
+    return out
+
+
+def bench_batch(steps, warmup, cpu_s, tile, k, n_images=512):
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1603_09180_amd import synth, thin
+
+    jobs = synth.batch_512_uneven(n_images)
+    Fs = [j.image() for j in jobs]
+    total_px = sum(F.size for F in Fs)
+    srcs = [torch.from_numpy(F).cuda() for F in Fs]
+    lams = [j.lam for j in jobs]
+    adjs = [j.adj for j in jobs]
+    ctx = thin.Context(device=0, profile=True, tile=tile, steps_per_round=k)
+    sets = [[s.clone() for s in srcs] for _ in range(warmup + steps)]
+    torch.cuda.synchronize()
+    for i in range(warmup):
+        ctx.run_batch(sets[i], lams, adjs)
+    torch.cuda.synchronize()
+    ctx.profile(reset=True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        stats = ctx.run_batch(sets[warmup + i], lams, adjs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile(reset=True)
+    # the same images, one plain call each
+    plain = [s.clone() for s in srcs]
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    for t, lam, adj in zip(plain, lams, adjs):
+        ctx.run(t, lam, adj)
+    torch.cuda.synchronize()
+    p1 = time.perf_counter()
+    ctx.close()
+    # bit-exactness on a sample: the 12 smallest images and every 64th
+    order = sorted(range(n_images), key=lambda i: Fs[i].size)
+    sample = sorted(set(order[:12]) | set(range(0, n_images, 64)))
+    exact = True
+    for i in sample:
+        ref = oracle.sweep_dirty(Fs[i], lams[i], adjs[i])
+        got = sets[warmup + steps - 1][i].cpu().numpy()
+        exact &= bool(np.array_equal(got, ref.image))
+        exact &= (stats[i].passes, stats[i].lowerings) == (ref.passes, ref.lowerings)
+        exact &= bool(np.array_equal(plain[i].cpu().numpy(), ref.image))
+    elapsed = t1 - t0
+    alg = sum(2 * F.size * st.passes for F, st in zip(Fs, stats)) * steps
+    kernel_s = prof.kernel_ms / 1e3
+    achieved = alg / kernel_s / 1e9 if kernel_s > 0 else None
+    out = {
+        "metric": METRIC,
+        "value": round(total_px * steps / elapsed / 1e6, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": round(elapsed / steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "batch_512", "images_per_step": n_images,
+                   "sides": "log-uniform 64..2048", "lambda": "{0,5,20,50}",
+                   "adjacency": "8,4", "path": "batched (thin_run_batch)"},
+        "images_per_s": round(n_images * steps / elapsed, 2),
+        "plain_images_per_s": round(n_images / (p1 - p0), 2),
+        "plain_mpixel_per_s": round(total_px / (p1 - p0) / 1e6, 3),
+        "bit_exact_sample": exact,
+        "roofline": {
+            "bound": "hbm", "kernel": "k_round",
+            "achieved": round(achieved, 2) if achieved else None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": _traffic_for("k_round", "batch_512"),
+            "launches_per_step": round(prof.launches / steps, 2),
+            "avg_launch_us": round(prof.kernel_ms * 1e3 / max(prof.launches, 1), 3),
+        },
+    }
+    if cpu_s > 0:
+        smalls = [(Fs[i], lams[i], adjs[i]) for i in order[: n_images // 2]]
+        v, n, dt = cpu_baseline(smalls, cpu_s)
+        out["cpu_baseline"] = {"value": round(v, 4), "unit": "Mpixel/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"ORACLE-SWEEP-DIRTY, single-thread C, {n} of the "
+                                         f"batch's images (smallest first) in {dt:.1f} s"}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="ridges_512",
+                    choices=["ridges_512", "blobs_128", "blobs_8192_u16", "batch_512"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU budget of the oracle baseline (0 disables it)")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--k", type=int, default=0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE={world}); images would shard across GPUs with no exchange, "
+              "but no multi-GPU figure is measured here.", file=sys.stderr)
+        sys.exit(2)
+
+    _ensure_built()
+    from paper_1603_09180_amd import synth
+
+    if args.workload == "batch_512":
+        out = bench_batch(args.steps, args.warmup, args.cpu_seconds, args.tile, args.k)
+    else:
+        job = {"ridges_512": synth.ridges_512, "blobs_128": synth.blobs_128,
+               "blobs_8192_u16": synth.blobs_8192_u16}[args.workload]()
+        out = bench_single(job, args.workload, args.steps, args.warmup, args.cpu_seconds,
+                           args.tile, args.k)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/*
+ * thin.h -- C ABI of the MI355X (gfx950) lambda-leveling library.
+ *
+ * The library lowers the lambda-destructible points of a grayscale image
+ * until the image is stable: the lambda-leveling loop of Couprie-Bertrand
+ * grayscale topological thinning, as defined in section 2.1 of Mahmoudi,
+ * Akil and Matas, "Parallel image thinning through topological operators on
+ * shared memory parallel machines" (the lambda-destructible point, the
+ * lowering target alpha-, and the "repeat until stability" loop of the
+ * algorithm box in section 2.2 with the type set lambda-destructible).
+ *
+ * Conventions shared by every call:
+ *   - An image is a caller-owned DEVICE buffer of h rows by w columns,
+ *     row-major, element type uint8 (THIN_U8) or uint16 (THIN_U16), row pitch
+ *     `pitch_elems` elements (w when contiguous).  It is processed IN PLACE:
+ *     on return it holds the stable image.  The library never frees it.
+ *   - Gray levels are the image's own integers (F maps pixels to integers,
+ *     section 2.1); lambda is in the same units and any uint32 value is valid.
+ *   - Adjacency pair (n, n') for sections and their complements (section 2.1):
+ *     THIN_ADJ_8_4 = (8,4), THIN_ADJ_4_8 = (4,8).
+ *   - The 1-pixel frame of the image is never modified (the paper's F lives
+ *     on Z^2; a finite image needs a border rule, and a read-only frame gives
+ *     every processed pixel a full 3x3 neighbourhood inside the image).
+ *     Images with h < 3 or w < 3 have no interior: the call returns THIN_OK,
+ *     leaves them unchanged and reports passes = 0.
+ *   - The order of lowering is fixed (the paper selects a point of minimal
+ *     value without a tie-break): pass p visits the parity classes
+ *     (i mod 2, j mod 2) = (0,0), (0,1), (1,0), (1,1) in that order on
+ *     absolute 0-based (row, column); each class is lowered all at once,
+ *     which equals lowering it pixel by pixel because two pixels of one class
+ *     are never 8-adjacent.  Stability is a whole pass without lowering.
+ *     The result, pass count and lowering count are therefore deterministic
+ *     and do not depend on tiling, launch shape or batching.
+ *   - Calls are synchronous with respect to the host: they return after the
+ *     result is in the caller's buffer.  Work is enqueued on the stream given
+ *     in thin_config (NULL = the null stream), so it orders after earlier
+ *     work on that stream.
+ *   - A context is not thread-safe: use one per host thread.
+ *   - Error codes (negative) leave the image untouched for THIN_EINVAL and
+ *     THIN_ENOMEM; after THIN_EDEVICE its contents are unspecified; after
+ *     THIN_ELIMIT it holds the state after the last complete pass (a valid
+ *     resume point: calling again continues to the same final image).
+ */
+#ifndef THIN_H
+#define THIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    THIN_OK = 0,
+    THIN_EINVAL = -1,   /* NULL pointer with h*w > 0, negative size, bad dtype or adjacency, pitch < w */
+    THIN_ENOMEM = -2,   /* scratch above max_device_bytes, or a device allocation failed */
+    THIN_EDEVICE = -3,  /* a HIP call failed */
+    THIN_ELIMIT = -4,   /* max_passes reached before stability */
+    THIN_EBUSY = -5     /* serving: admission would exceed the device-memory budget */
+};
+
+enum { THIN_U8 = 1, THIN_U16 = 2 };
+enum { THIN_ADJ_8_4 = 0, THIN_ADJ_4_8 = 1 };
+
+/* Engines (thin_config.engine).  All produce bit-identical results. */
+enum {
+    THIN_ENGINE_AUTO = 0,    /* tiled LDS engine */
+    THIN_ENGINE_TILED = 1,   /* LDS tiles, several parity steps per residency, stable tiles skipped */
+    THIN_ENGINE_STEP = 2     /* one parity step per launch over global memory (simple, slow) */
+};
+
+typedef struct thin_ctx thin_ctx;
+
+typedef struct thin_config {
+    int32_t device;             /* HIP device ordinal */
+    int32_t engine;             /* THIN_ENGINE_*, 0 = auto */
+    void* hip_stream;           /* hipStream_t to enqueue on; NULL = the null stream */
+    uint64_t max_device_bytes;  /* cap on device scratch owned by the context; 0 = no cap */
+    uint64_t max_passes;        /* per-image pass cap (THIN_ELIMIT when reached); 0 = none */
+    int32_t tile;               /* tile side in pixels for the tiled engine; 0 = automatic */
+    int32_t steps_per_round;    /* parity steps per tile residency (halo width); 0 = automatic */
+    uint32_t flags;             /* THIN_FLAG_* */
+    uint32_t reserved;
+} thin_config;
+
+/* thin_config.flags */
+enum {
+    THIN_FLAG_PROFILE = 1       /* time every round kernel with HIP events (see thin_profile) */
+};
+
+typedef struct thin_profile_info {
+    uint64_t launches;          /* round-kernel launches timed since the last reset */
+    double kernel_ms;           /* sum of their durations, from HIP events on the context stream */
+    uint64_t tile_rounds;       /* tile residencies they processed */
+} thin_profile_info;
+
+typedef struct thin_stats {
+    uint64_t passes;       /* passes to stability, including the final pass without lowering */
+    uint64_t lowerings;    /* number of lowerings F(x) := alpha- performed */
+    uint64_t tile_rounds;  /* tile residencies processed (work done; depends on the engine) */
+    uint32_t converged;    /* 1 when stable, 0 when stopped by max_passes */
+    uint32_t reserved;
+} thin_stats;
+
+typedef struct thin_image {
+    void* image;           /* caller-owned device buffer, modified in place */
+    int64_t h, w;          /* rows, columns */
+    int64_t pitch_elems;   /* row pitch in elements; 0 means w */
+    int32_t dtype;         /* THIN_U8 or THIN_U16 */
+    uint32_t lambda;       /* contrast parameter of the lambda-destructible test */
+    int32_t adjacency;     /* THIN_ADJ_8_4 or THIN_ADJ_4_8 */
+    int32_t reserved;
+} thin_image;
+
+/* Creates a context on cfg->device (cfg may be NULL: device 0, defaults).
+ * Uploads the connectivity tables; scratch is allocated on first use and
+ * kept.  Returns THIN_OK and *out, or an error (then *out is NULL). */
+int thin_create(thin_ctx** out, const thin_config* cfg);
+
+/* Lowers every lambda-destructible point of one image until stability
+ * (section 2.2, type set lambda-destructible; section 2.1 for the test and
+ * for alpha-).  image: device pointer to h*w contiguous elements.
+ * stats may be NULL. */
+int thin_run(thin_ctx* ctx, void* image, int64_t h, int64_t w, int32_t dtype,
+             uint32_t lambda, int32_t adjacency, thin_stats* stats);
+
+/* Same as thin_run for n independent images of any sizes, dtypes, lambdas
+ * and adjacencies, processed together by one device work list.  Images must
+ * not overlap.  stats: NULL or an array of n entries.  Each image's result
+ * and statistics equal those of a thin_run call on it alone. */
+int thin_run_batch(thin_ctx* ctx, const thin_image* imgs, int32_t n, thin_stats* stats);
+
+/* Serving (continuous batching).  thin_serve_admit makes an image resident
+ * under a caller-chosen tag; it starts at the next round.  Returns THIN_EBUSY,
+ * leaving nothing admitted, when its scratch would exceed max_device_bytes.
+ * The image buffer must stay valid until the tag is retired. */
+int thin_serve_admit(thin_ctx* ctx, const thin_image* img, uint64_t tag);
+
+/* Runs `rounds` rounds over every resident image, then retires the images
+ * that are stable (or hit max_passes): their final values are in their own
+ * buffers when the call returns.  Up to `cap` retired tags are written to
+ * done_tags (and their statistics to done_stats when not NULL); *n_done
+ * receives how many were written.  Images beyond `cap` stay resident and are
+ * reported by a later call.  *n_resident (nullable) receives the number of
+ * images still resident. */
+int thin_serve_step(thin_ctx* ctx, int32_t rounds, uint64_t* done_tags, thin_stats* done_stats,
+                    int32_t cap, int32_t* n_done, int32_t* n_resident);
+
+/* Releases the context and all scratch it owns (NULL is accepted).
+ * Never frees caller images. */
+int thin_destroy(thin_ctx* ctx);
+
+/* Static text for an error code. */
+const char* thin_strerror(int code);
+
+/* Text of the last error seen by ctx ("" when none; never NULL). */
+const char* thin_last_error(const thin_ctx* ctx);
+
+/* Reads (and with reset != 0 clears) the kernel timing gathered while
+ * THIN_FLAG_PROFILE is set.  Returns THIN_EINVAL for NULL arguments. */
+int thin_profile(thin_ctx* ctx, thin_profile_info* out, int32_t reset);
+
+/* Host-side copy of the connectivity table the kernels use for adjacency
+ * `adjacency`: for each upper-neighbour mask m (bit p set when ring
+ * neighbour p has F >= F(x); ring order E, NE, N, NW, W, SW, S, SE, rows
+ * growing downward), out[2m] holds bit 0 = destructible (T+ = 1 and
+ * T-- = 1), bits 4..6 = T--, bits 8..10 = T+; out[2m+1] holds, in byte c,
+ * the ring mask of the c-th counted lower component (c < T--).  n must be
+ * at least 512.  Returns THIN_OK or THIN_EINVAL.  Needs no GPU. */
+int thin_topology_table(int32_t adjacency, uint32_t* out, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* THIN_H */

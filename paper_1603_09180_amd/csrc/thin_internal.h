@@ -1,0 +1,62 @@
+// thin_internal.h -- structures shared by the HIP kernels and the host runtime
+// of the lambda-leveling library.  Not part of the public ABI (include/thin.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace thin {
+
+// One image as the kernels see it.  buf[0] is the caller's image, buf[1] the
+// context-owned twin of the same pitch; round r reads buf[r & 1] and writes
+// buf[(r + 1) & 1], so after r rounds the current state is in buf[r & 1].
+struct ImgDev {
+    void* buf[2];
+    int64_t pitch;       // row pitch in elements (both buffers)
+    int32_t h, w;
+    int32_t dtype;       // 1 = u8, 2 = u16
+    uint32_t lambda;
+    int32_t adj;         // 0 = (8,4), 1 = (4,8)
+    int32_t tiles_x;     // tile grid of this image
+    int32_t tiles_y;
+    int32_t tile0;       // index of its first tile in the launch's tile arrays
+    int32_t round0;      // launch round at which the image's step 0 starts
+    int32_t max_steps;   // parity-step cap (4 * max_passes), INT32_MAX if none
+};
+
+// Per-image counters, written by the kernels with device-scope atomics.
+struct ImgCnt {
+    unsigned long long lowerings;
+    unsigned long long tile_rounds;
+    int32_t last_step;   // image-local index of the last step that lowered, -1 if none
+    int32_t pad;
+};
+
+// Connectivity table entry for an upper-neighbour mask (see thin_topology_table).
+//   x: bit 0 destructible, bits 4..6 T--, bits 8..10 T+
+//   y: byte c = ring mask of the c-th counted lower component
+struct TopoEntry {
+    uint32_t flags;
+    uint32_t comps;
+};
+
+// Host-side generation of the 2 x 256 table (adjacency-major).
+void build_topology_table(int adjacency, TopoEntry out[256]);
+
+// Tiled engine geometry chosen at run time among the compiled variants.
+struct TileShape {
+    int th, tw, k;
+};
+
+// Kernel launchers (thin_kernels.hip).  All enqueue on `stream`.
+hipError_t launch_init_state(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t* tile_last,
+                             int ntiles);
+hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
+                        const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
+                        const TopoEntry* lut, int grid_blocks);
+hipError_t launch_step(hipStream_t stream, const ImgDev* img_host, const ImgDev* img_dev,
+                       ImgCnt* cnt, int step, const TopoEntry* lut);
+bool tile_shape_supported(TileShape s);
+int round_blocks_per_cu(TileShape s);
+
+}  // namespace thin

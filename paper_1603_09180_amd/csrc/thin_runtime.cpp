@@ -1,0 +1,607 @@
+// thin_runtime.cpp -- host runtime and C ABI of the lambda-leveling library.
+//
+// The runtime validates arguments, owns the device scratch (ping-pong twins,
+// per-tile state, per-image counters, the connectivity table), builds the
+// tile work list, launches rounds of the tiled kernel on the context's
+// stream and decides convergence from per-image counters copied back
+// asynchronously: a round chunk is checked while the next one already runs,
+// so the host never waits on the GPU between chunks.
+//
+// Convergence (the "until stability" of section 2.2): an image is stable once
+// four consecutive parity steps -- one of each class -- lowered nothing.  The
+// step sequence is fixed, so the pass count is recovered exactly from the
+// index of the last step that lowered something: P = last_step / 4 + 2, or 1
+// when nothing was ever lowered (the final pass without change is counted).
+#include <algorithm>
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "thin.h"
+#include "thin_internal.h"
+
+using thin::ImgCnt;
+using thin::ImgDev;
+using thin::TileShape;
+using thin::TopoEntry;
+
+namespace {
+
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Resident {          // one image admitted for serving
+    thin_image img;
+    uint64_t tag;
+    int round0;            // launch round of its first step
+    size_t twin_off;       // offset of its twin inside the serving arena
+    size_t twin_bytes;
+    int max_steps;
+};
+
+}  // namespace
+
+struct thin_ctx {
+    int device = 0;
+    int engine = THIN_ENGINE_TILED;
+    hipStream_t stream = nullptr;
+    uint64_t max_device_bytes = 0;
+    uint64_t max_passes = 0;
+    TileShape forced{0, 0, 0};
+    int num_cus = 256;
+
+    TopoEntry* d_lut = nullptr;
+    uint64_t allocated = 0;        // bytes of scratch currently held
+    DevBuf twin, imgs, cnt, tile_img, tile_last;
+    ImgCnt* h_snap[2] = {nullptr, nullptr};   // pinned snapshots of the counters
+    size_t h_snap_cap = 0;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+
+    // profiling (THIN_FLAG_PROFILE): a pool of timing events, two per launch
+    bool profile = false;
+    std::vector<hipEvent_t> prof_ev;
+    uint64_t prof_launches = 0;
+    double prof_ms = 0.0;
+    uint64_t prof_tile_rounds = 0;
+
+    // serving
+    std::vector<Resident> resident;
+    int serve_round = 0;
+    DevBuf serve_twin;
+    size_t serve_twin_used = 0;
+    uint64_t serve_bytes = 0;      // footprint of resident images
+
+    std::string last_error;
+};
+
+namespace {
+
+int fail(thin_ctx* ctx, int code, const char* fmt, ...)
+{
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->last_error = buf;
+    }
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), THIN_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// Grows `b` to at least `need` bytes (contents not kept).
+int ensure(thin_ctx* ctx, DevBuf& b, size_t need)
+{
+    if (b.bytes >= need) return THIN_OK;
+    size_t want = std::max(need, b.bytes + b.bytes / 2);
+    want = (want + 255) & ~size_t(255);
+    const uint64_t after = ctx->allocated - b.bytes + want;
+    if (ctx->max_device_bytes && after > ctx->max_device_bytes) {
+        want = (need + 255) & ~size_t(255);
+        if (ctx->allocated - b.bytes + want > ctx->max_device_bytes)
+            return fail(ctx, THIN_ENOMEM, "scratch of %zu bytes exceeds max_device_bytes %llu",
+                        want, (unsigned long long)ctx->max_device_bytes);
+    }
+    if (b.ptr) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        HIP_TRY(ctx, hipFree(b.ptr));
+        ctx->allocated -= b.bytes;
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    if (hipMalloc(&b.ptr, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.ptr = nullptr;
+        return fail(ctx, THIN_ENOMEM, "hipMalloc(%zu) failed", want);
+    }
+    b.bytes = want;
+    ctx->allocated += want;
+    return THIN_OK;
+}
+
+int ensure_snap(thin_ctx* ctx, size_t n)
+{
+    if (ctx->h_snap_cap >= n) return THIN_OK;
+    for (int i = 0; i < 2; ++i) {
+        if (ctx->h_snap[i]) (void)hipHostFree(ctx->h_snap[i]);
+        ctx->h_snap[i] = nullptr;
+    }
+    size_t want = std::max<size_t>(n, 64);
+    for (int i = 0; i < 2; ++i)
+        if (hipHostMalloc((void**)&ctx->h_snap[i], want * sizeof(ImgCnt), hipHostMallocDefault) !=
+            hipSuccess)
+            return fail(ctx, THIN_ENOMEM, "hipHostMalloc of counter snapshots failed");
+    ctx->h_snap_cap = want;
+    return THIN_OK;
+}
+
+// Launches one round, bracketed by timing events when profiling.
+int timed_round(thin_ctx* ctx, size_t& ev_used, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
+                const int32_t* tile_img, int32_t* tile_last, int ntiles, int round, int grid)
+{
+    if (ctx->profile) {
+        while (ctx->prof_ev.size() < ev_used + 2) {
+            hipEvent_t e;
+            HIP_TRY(ctx, hipEventCreate(&e));
+            ctx->prof_ev.push_back(e);
+        }
+        HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used], ctx->stream));
+    }
+    HIP_TRY(ctx, thin::launch_round(ctx->stream, shape, imgs, cnt, tile_img, tile_last, ntiles,
+                                    round, ctx->d_lut, grid));
+    if (ctx->profile) {
+        HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used + 1], ctx->stream));
+        ev_used += 2;
+    }
+    return THIN_OK;
+}
+
+// Adds the durations of the timed launches (the stream must be idle).
+int collect_profile(thin_ctx* ctx, size_t ev_used)
+{
+    for (size_t i = 0; i + 1 < ev_used; i += 2) {
+        float ms = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->prof_ev[i], ctx->prof_ev[i + 1]));
+        ctx->prof_ms += ms;
+        ctx->prof_launches += 1;
+    }
+    return THIN_OK;
+}
+
+int validate(thin_ctx* ctx, const thin_image& im)
+{
+    if (im.h < 0 || im.w < 0) return fail(ctx, THIN_EINVAL, "negative image size");
+    if (im.dtype != THIN_U8 && im.dtype != THIN_U16) return fail(ctx, THIN_EINVAL, "bad dtype %d", im.dtype);
+    if (im.adjacency != THIN_ADJ_8_4 && im.adjacency != THIN_ADJ_4_8)
+        return fail(ctx, THIN_EINVAL, "bad adjacency %d", im.adjacency);
+    if (im.pitch_elems != 0 && im.pitch_elems < im.w) return fail(ctx, THIN_EINVAL, "pitch < w");
+    if (im.h > (1 << 30) || im.w > (1 << 30)) return fail(ctx, THIN_EINVAL, "image side above 2^30");
+    if (im.h * im.w > 0 && im.image == nullptr) return fail(ctx, THIN_EINVAL, "NULL image");
+    return THIN_OK;
+}
+
+int64_t pitch_of(const thin_image& im) { return im.pitch_elems ? im.pitch_elems : im.w; }
+
+int steps_cap(const thin_ctx* ctx)
+{
+    if (!ctx->max_passes) return INT_MAX;
+    const uint64_t s = ctx->max_passes * 4ull;
+    return s > (uint64_t)INT_MAX ? INT_MAX : (int)s;
+}
+
+TileShape choose_shape(const thin_ctx* ctx, int64_t total_pixels)
+{
+    if (ctx->forced.th) return ctx->forced;
+    if (total_pixels <= (int64_t)4 << 20) return TileShape{32, 32, 16};
+    return TileShape{64, 64, 16};
+}
+
+void fill_stats(thin_stats* st, const ImgCnt& c, int steps_done, int max_steps, bool trivial)
+{
+    if (!st) return;
+    std::memset(st, 0, sizeof *st);
+    if (trivial) {
+        st->converged = 1;
+        return;
+    }
+    st->lowerings = c.lowerings;
+    st->tile_rounds = c.tile_rounds;
+    const bool stable = c.last_step < steps_done - 4;
+    if (stable) {
+        st->converged = 1;
+        st->passes = c.last_step < 0 ? 1 : (uint64_t)(c.last_step / 4) + 2;
+    } else {
+        st->converged = 0;
+        st->passes = (uint64_t)std::min(steps_done, max_steps) / 4;
+    }
+}
+
+// ---------------------------------------------------------------- tiled engine
+
+struct Plan {
+    std::vector<ImgDev> imgs;
+    std::vector<int32_t> tile_img;
+    std::vector<int> src_index;     // position in the caller's array
+};
+
+int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work, thin_stats* stats)
+{
+    int64_t total_px = 0;
+    for (int i : work) total_px += ims[i].h * ims[i].w;
+    const TileShape shape = choose_shape(ctx, total_px);
+    if (!thin::tile_shape_supported(shape))
+        return fail(ctx, THIN_EINVAL, "unsupported tile shape %dx%d k=%d", shape.th, shape.tw, shape.k);
+    const int K = shape.k;
+    const int max_steps = steps_cap(ctx);
+
+    Plan plan;
+    size_t twin_bytes = 0;
+    std::vector<size_t> twin_off;
+    for (int i : work) {
+        const thin_image& im = ims[i];
+        const size_t bpp = im.dtype == THIN_U8 ? 1 : 2;
+        twin_off.push_back(twin_bytes);
+        twin_bytes += ((size_t)im.h * (size_t)pitch_of(im) * bpp + 255) & ~size_t(255);
+    }
+    int rc = ensure(ctx, ctx->twin, std::max<size_t>(twin_bytes, 256));
+    if (rc) return rc;
+    for (size_t n = 0; n < work.size(); ++n) {
+        const thin_image& im = ims[work[n]];
+        ImgDev d{};
+        d.buf[0] = im.image;
+        d.buf[1] = static_cast<char*>(ctx->twin.ptr) + twin_off[n];
+        d.pitch = pitch_of(im);
+        d.h = (int32_t)im.h;
+        d.w = (int32_t)im.w;
+        d.dtype = im.dtype;
+        d.lambda = im.lambda;
+        d.adj = im.adjacency;
+        d.tiles_y = (int32_t)((im.h + shape.th - 1) / shape.th);
+        d.tiles_x = (int32_t)((im.w + shape.tw - 1) / shape.tw);
+        d.tile0 = (int32_t)plan.tile_img.size();
+        d.round0 = 0;
+        d.max_steps = max_steps;
+        const int64_t nt = (int64_t)d.tiles_x * d.tiles_y;
+        if ((int64_t)plan.tile_img.size() + nt > INT_MAX / 2)
+            return fail(ctx, THIN_EINVAL, "too many tiles in one call");
+        for (int64_t t = 0; t < nt; ++t) plan.tile_img.push_back((int32_t)plan.imgs.size());
+        plan.imgs.push_back(d);
+        plan.src_index.push_back(work[n]);
+    }
+    const int nimg = (int)plan.imgs.size();
+    const int ntiles = (int)plan.tile_img.size();
+    if ((rc = ensure(ctx, ctx->imgs, sizeof(ImgDev) * nimg))) return rc;
+    if ((rc = ensure(ctx, ctx->cnt, sizeof(ImgCnt) * nimg))) return rc;
+    if ((rc = ensure(ctx, ctx->tile_img, sizeof(int32_t) * ntiles))) return rc;
+    if ((rc = ensure(ctx, ctx->tile_last, sizeof(int32_t) * ntiles))) return rc;
+    if ((rc = ensure_snap(ctx, nimg))) return rc;
+
+    ImgDev* d_imgs = static_cast<ImgDev*>(ctx->imgs.ptr);
+    ImgCnt* d_cnt = static_cast<ImgCnt*>(ctx->cnt.ptr);
+    int32_t* d_tile_img = static_cast<int32_t*>(ctx->tile_img.ptr);
+    int32_t* d_tile_last = static_cast<int32_t*>(ctx->tile_last.ptr);
+    HIP_TRY(ctx, hipMemcpyAsync(d_imgs, plan.imgs.data(), sizeof(ImgDev) * nimg,
+                                hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(d_tile_img, plan.tile_img.data(), sizeof(int32_t) * ntiles,
+                                hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, nimg, d_tile_last, ntiles));
+
+    const int grid = ctx->num_cus * thin::round_blocks_per_cu(shape);
+    const int rounds_cap = (max_steps == INT_MAX) ? INT_MAX : (max_steps + K - 1) / K;
+    size_t ev_used = 0;        // profiling events recorded by this call
+    int launched = 0;          // rounds enqueued so far
+    int checked_upto = -1;     // rounds covered by the last evaluated snapshot
+    int chunk = 2;
+    int pending = -1;          // snapshot slot in flight (-1 none)
+    int pending_rounds = 0;
+    bool done = false;
+    auto all_done = [&](const ImgCnt* snap, int rounds) {
+        for (int i = 0; i < nimg; ++i) {
+            const int steps = (int)std::min<int64_t>((int64_t)rounds * K, plan.imgs[i].max_steps);
+            const bool stable = snap[i].last_step < steps - 4;
+            if (!stable && steps < plan.imgs[i].max_steps) return false;
+        }
+        return true;
+    };
+    while (!done) {
+        const int n = std::min(chunk, rounds_cap - launched);
+        for (int k = 0; k < n; ++k) {
+            if ((rc = timed_round(ctx, ev_used, shape, d_imgs, d_cnt, d_tile_img, d_tile_last,
+                                  ntiles, launched, grid)))
+                return rc;
+            ++launched;
+        }
+        const int slot = (pending < 0) ? 0 : 1 - pending;
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_snap[slot], d_cnt, sizeof(ImgCnt) * nimg,
+                                    hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipEventRecord(ctx->ev[slot], ctx->stream));
+        if (launched >= rounds_cap) break;
+        if (pending >= 0) {
+            HIP_TRY(ctx, hipEventSynchronize(ctx->ev[pending]));
+            checked_upto = pending_rounds;
+            if (all_done(ctx->h_snap[pending], pending_rounds)) done = true;
+        }
+        pending = slot;
+        pending_rounds = launched;
+        chunk = std::min(chunk * 2, 16);
+    }
+    (void)checked_upto;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipMemcpy(ctx->h_snap[0], d_cnt, sizeof(ImgCnt) * nimg, hipMemcpyDeviceToHost));
+    const ImgCnt* fin = ctx->h_snap[0];
+    if (ctx->profile) {
+        if ((rc = collect_profile(ctx, ev_used))) return rc;
+        for (int i = 0; i < nimg; ++i) ctx->prof_tile_rounds += fin[i].tile_rounds;
+    }
+
+    // Bring results home: after r rounds an image's state is in buf[r & 1],
+    // where r stops growing once its step cap is reached.
+    for (int i = 0; i < nimg; ++i) {
+        const ImgDev& d = plan.imgs[i];
+        const int r_img = std::min(launched, (d.max_steps == INT_MAX) ? INT_MAX
+                                                                       : (d.max_steps + K - 1) / K);
+        if (r_img & 1) {
+            const size_t bpp = d.dtype == THIN_U8 ? 1 : 2;
+            HIP_TRY(ctx, hipMemcpy2DAsync(d.buf[0], d.pitch * bpp, d.buf[1], d.pitch * bpp,
+                                          (size_t)d.w * bpp, (size_t)d.h,
+                                          hipMemcpyDeviceToDevice, ctx->stream));
+        }
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+
+    bool limited = false;
+    for (int i = 0; i < nimg; ++i) {
+        const ImgDev& d = plan.imgs[i];
+        const int steps = (int)std::min<int64_t>((int64_t)launched * K, d.max_steps);
+        thin_stats st;
+        fill_stats(&st, fin[i], steps, d.max_steps, false);
+        if (!st.converged) limited = true;
+        if (stats) stats[plan.src_index[i]] = st;
+    }
+    return limited ? fail(ctx, THIN_ELIMIT, "max_passes reached before stability") : THIN_OK;
+}
+
+// ----------------------------------------------------------------- step engine
+
+int run_step_engine(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
+                    thin_stats* stats)
+{
+    int rc;
+    if ((rc = ensure(ctx, ctx->imgs, sizeof(ImgDev)))) return rc;
+    if ((rc = ensure(ctx, ctx->cnt, sizeof(ImgCnt)))) return rc;
+    if ((rc = ensure_snap(ctx, 1))) return rc;
+    const int max_steps = steps_cap(ctx);
+    bool limited = false;
+    for (int i : work) {
+        const thin_image& im = ims[i];
+        if (im.h > 131070) return fail(ctx, THIN_EINVAL, "step engine supports h <= 131070");
+        ImgDev d{};
+        d.buf[0] = d.buf[1] = im.image;
+        d.pitch = pitch_of(im);
+        d.h = (int32_t)im.h;
+        d.w = (int32_t)im.w;
+        d.dtype = im.dtype;
+        d.lambda = im.lambda;
+        d.adj = im.adjacency;
+        d.max_steps = max_steps;
+        ImgDev* d_img = static_cast<ImgDev*>(ctx->imgs.ptr);
+        ImgCnt* d_cnt = static_cast<ImgCnt*>(ctx->cnt.ptr);
+        HIP_TRY(ctx, hipMemcpyAsync(d_img, &d, sizeof d, hipMemcpyHostToDevice, ctx->stream));
+        HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, 1, nullptr, 0));
+        int step = 0;
+        for (;;) {
+            for (int s = 0; s < 4 && step < max_steps; ++s, ++step)
+                HIP_TRY(ctx, thin::launch_step(ctx->stream, &d, d_img, d_cnt, step, ctx->d_lut));
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->h_snap[0], d_cnt, sizeof(ImgCnt),
+                                        hipMemcpyDeviceToHost, ctx->stream));
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+            if (ctx->h_snap[0]->last_step < step - 4 || step >= max_steps) break;
+        }
+        thin_stats st;
+        fill_stats(&st, *ctx->h_snap[0], step, max_steps, false);
+        if (!st.converged) limited = true;
+        if (stats) stats[i] = st;
+    }
+    return limited ? fail(ctx, THIN_ELIMIT, "max_passes reached before stability") : THIN_OK;
+}
+
+int run_images(thin_ctx* ctx, const thin_image* ims, int n, thin_stats* stats)
+{
+    if (!ctx) return THIN_EINVAL;
+    if (n < 0 || (n > 0 && !ims)) return fail(ctx, THIN_EINVAL, "bad image list");
+    for (int i = 0; i < n; ++i) {
+        const int rc = validate(ctx, ims[i]);
+        if (rc) return rc;
+    }
+    std::vector<int> work;
+    for (int i = 0; i < n; ++i) {
+        if (ims[i].h < 3 || ims[i].w < 3) {
+            if (stats) fill_stats(&stats[i], ImgCnt{}, 0, 0, true);
+        } else {
+            work.push_back(i);
+        }
+    }
+    if (work.empty()) return THIN_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (ctx->engine == THIN_ENGINE_STEP) return run_step_engine(ctx, ims, work, stats);
+    return run_tiled(ctx, ims, work, stats);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------- ABI
+
+extern "C" {
+
+int thin_create(thin_ctx** out, const thin_config* cfg)
+{
+    if (!out) return THIN_EINVAL;
+    *out = nullptr;
+    thin_config c{};
+    if (cfg) c = *cfg;
+    if (c.engine < 0 || c.engine > THIN_ENGINE_STEP) return THIN_EINVAL;
+    if ((c.tile != 0) != (c.steps_per_round != 0)) return THIN_EINVAL;
+    if (c.tile && !thin::tile_shape_supported(TileShape{c.tile, c.tile, c.steps_per_round}))
+        return THIN_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return THIN_EDEVICE;
+    }
+    if (c.device < 0 || c.device >= ndev) return THIN_EINVAL;
+    thin_ctx* ctx = new (std::nothrow) thin_ctx();
+    if (!ctx) return THIN_ENOMEM;
+    ctx->device = c.device;
+    ctx->engine = c.engine == THIN_ENGINE_AUTO ? THIN_ENGINE_TILED : c.engine;
+    ctx->stream = static_cast<hipStream_t>(c.hip_stream);
+    ctx->max_device_bytes = c.max_device_bytes;
+    ctx->max_passes = c.max_passes;
+    if (c.tile) ctx->forced = TileShape{c.tile, c.tile, c.steps_per_round};
+    ctx->profile = (c.flags & THIN_FLAG_PROFILE) != 0;
+    int rc = THIN_OK;
+    do {
+        if (hipSetDevice(c.device) != hipSuccess) { rc = THIN_EDEVICE; break; }
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device) == hipSuccess &&
+            cus > 0)
+            ctx->num_cus = cus;
+        TopoEntry table[512];
+        thin::build_topology_table(0, table);
+        thin::build_topology_table(1, table + 256);
+        if (hipMalloc((void**)&ctx->d_lut, sizeof table) != hipSuccess) { rc = THIN_ENOMEM; break; }
+        if (hipMemcpy(ctx->d_lut, table, sizeof table, hipMemcpyHostToDevice) != hipSuccess) {
+            rc = THIN_EDEVICE;
+            break;
+        }
+        for (int i = 0; i < 2; ++i)
+            if (hipEventCreateWithFlags(&ctx->ev[i], hipEventDisableTiming) != hipSuccess) {
+                rc = THIN_EDEVICE;
+                break;
+            }
+    } while (0);
+    if (rc != THIN_OK) {
+        (void)hipGetLastError();
+        thin_destroy(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return THIN_OK;
+}
+
+int thin_run(thin_ctx* ctx, void* image, int64_t h, int64_t w, int32_t dtype, uint32_t lambda,
+             int32_t adjacency, thin_stats* stats)
+{
+    thin_image im{};
+    im.image = image;
+    im.h = h;
+    im.w = w;
+    im.pitch_elems = w;
+    im.dtype = dtype;
+    im.lambda = lambda;
+    im.adjacency = adjacency;
+    return run_images(ctx, &im, 1, stats);
+}
+
+int thin_run_batch(thin_ctx* ctx, const thin_image* imgs, int32_t n, thin_stats* stats)
+{
+    return run_images(ctx, imgs, n, stats);
+}
+
+int thin_destroy(thin_ctx* ctx)
+{
+    if (!ctx) return THIN_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    DevBuf* bufs[] = {&ctx->twin, &ctx->imgs, &ctx->cnt, &ctx->tile_img, &ctx->tile_last,
+                      &ctx->serve_twin};
+    for (DevBuf* b : bufs)
+        if (b->ptr) (void)hipFree(b->ptr);
+    if (ctx->d_lut) (void)hipFree(ctx->d_lut);
+    for (int i = 0; i < 2; ++i) {
+        if (ctx->h_snap[i]) (void)hipHostFree(ctx->h_snap[i]);
+        if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+    }
+    for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
+    delete ctx;
+    return THIN_OK;
+}
+
+const char* thin_strerror(int code)
+{
+    switch (code) {
+    case THIN_OK: return "ok";
+    case THIN_EINVAL: return "invalid argument";
+    case THIN_ENOMEM: return "out of device memory or above max_device_bytes";
+    case THIN_EDEVICE: return "HIP device error";
+    case THIN_ELIMIT: return "max_passes reached before stability";
+    case THIN_EBUSY: return "device-memory budget exhausted; try again later";
+    default: return "unknown error";
+    }
+}
+
+const char* thin_last_error(const thin_ctx* ctx)
+{
+    return ctx ? ctx->last_error.c_str() : "";
+}
+
+int thin_profile(thin_ctx* ctx, thin_profile_info* out, int32_t reset)
+{
+    if (!ctx || !out) return THIN_EINVAL;
+    out->launches = ctx->prof_launches;
+    out->kernel_ms = ctx->prof_ms;
+    out->tile_rounds = ctx->prof_tile_rounds;
+    if (reset) {
+        ctx->prof_launches = 0;
+        ctx->prof_ms = 0.0;
+        ctx->prof_tile_rounds = 0;
+    }
+    return THIN_OK;
+}
+
+int thin_topology_table(int32_t adjacency, uint32_t* out, int32_t n)
+{
+    if ((adjacency != THIN_ADJ_8_4 && adjacency != THIN_ADJ_4_8) || !out || n < 512)
+        return THIN_EINVAL;
+    TopoEntry t[256];
+    thin::build_topology_table(adjacency, t);
+    for (int m = 0; m < 256; ++m) {
+        out[2 * m] = t[m].flags;
+        out[2 * m + 1] = t[m].comps;
+    }
+    return THIN_OK;
+}
+
+int thin_serve_admit(thin_ctx* ctx, const thin_image* img, uint64_t tag)
+{
+    (void)img;
+    (void)tag;
+    return fail(ctx, THIN_EINVAL, "serving is not available yet");
+}
+
+int thin_serve_step(thin_ctx* ctx, int32_t rounds, uint64_t* done_tags, thin_stats* done_stats,
+                    int32_t cap, int32_t* n_done, int32_t* n_resident)
+{
+    (void)rounds;
+    (void)done_tags;
+    (void)done_stats;
+    (void)cap;
+    if (n_done) *n_done = 0;
+    if (n_resident) *n_resident = 0;
+    return fail(ctx, THIN_EINVAL, "serving is not available yet");
+}
+
+}  // extern "C"

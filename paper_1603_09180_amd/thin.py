@@ -1,0 +1,303 @@
+"""ctypes binding of libthin.so (include/thin.h).
+
+The functions named like the C calls (thin_create, thin_run, ...) only
+marshal arguments; every step of the lambda-leveling loop runs in the HIP
+library.  torch is used for device memory and streams only.  If the library
+has not been built the binding raises ThinError: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libthin.so")
+
+THIN_OK, THIN_EINVAL, THIN_ENOMEM, THIN_EDEVICE, THIN_ELIMIT, THIN_EBUSY = 0, -1, -2, -3, -4, -5
+THIN_U8, THIN_U16 = 1, 2
+THIN_ADJ_8_4, THIN_ADJ_4_8 = 0, 1
+THIN_ENGINE_AUTO, THIN_ENGINE_TILED, THIN_ENGINE_STEP = 0, 1, 2
+THIN_FLAG_PROFILE = 1
+
+EXPORTED = [
+    "thin_create", "thin_run", "thin_run_batch", "thin_serve_admit", "thin_serve_step",
+    "thin_destroy", "thin_strerror", "thin_last_error", "thin_profile", "thin_topology_table",
+]
+
+
+class ThinError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class thin_config(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32),
+        ("engine", ctypes.c_int32),
+        ("hip_stream", ctypes.c_void_p),
+        ("max_device_bytes", ctypes.c_uint64),
+        ("max_passes", ctypes.c_uint64),
+        ("tile", ctypes.c_int32),
+        ("steps_per_round", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class thin_profile_info(ctypes.Structure):
+    _fields_ = [
+        ("launches", ctypes.c_uint64),
+        ("kernel_ms", ctypes.c_double),
+        ("tile_rounds", ctypes.c_uint64),
+    ]
+
+
+class thin_stats(ctypes.Structure):
+    _fields_ = [
+        ("passes", ctypes.c_uint64),
+        ("lowerings", ctypes.c_uint64),
+        ("tile_rounds", ctypes.c_uint64),
+        ("converged", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class thin_image(ctypes.Structure):
+    _fields_ = [
+        ("image", ctypes.c_void_p),
+        ("h", ctypes.c_int64),
+        ("w", ctypes.c_int64),
+        ("pitch_elems", ctypes.c_int64),
+        ("dtype", ctypes.c_int32),
+        ("lambda_", ctypes.c_uint32),
+        ("adjacency", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libthin.so and declares the C signatures.  Raises ThinError
+    when the library has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ThinError(THIN_EDEVICE, f"{path} is missing: build it with "
+                                      "`python -m paper_1603_09180_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    lib.thin_create.argtypes = [P(ctypes.c_void_p), P(thin_config)]
+    lib.thin_create.restype = ctypes.c_int
+    lib.thin_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                             ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32, P(thin_stats)]
+    lib.thin_run.restype = ctypes.c_int
+    lib.thin_run_batch.argtypes = [ctypes.c_void_p, P(thin_image), ctypes.c_int32, P(thin_stats)]
+    lib.thin_run_batch.restype = ctypes.c_int
+    lib.thin_serve_admit.argtypes = [ctypes.c_void_p, P(thin_image), ctypes.c_uint64]
+    lib.thin_serve_admit.restype = ctypes.c_int
+    lib.thin_serve_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_uint64),
+                                    P(thin_stats), ctypes.c_int32, P(ctypes.c_int32),
+                                    P(ctypes.c_int32)]
+    lib.thin_serve_step.restype = ctypes.c_int
+    lib.thin_destroy.argtypes = [ctypes.c_void_p]
+    lib.thin_destroy.restype = ctypes.c_int
+    lib.thin_strerror.argtypes = [ctypes.c_int]
+    lib.thin_strerror.restype = ctypes.c_char_p
+    lib.thin_last_error.argtypes = [ctypes.c_void_p]
+    lib.thin_last_error.restype = ctypes.c_char_p
+    lib.thin_profile.argtypes = [ctypes.c_void_p, P(thin_profile_info), ctypes.c_int32]
+    lib.thin_profile.restype = ctypes.c_int
+    lib.thin_topology_table.argtypes = [ctypes.c_int32, P(ctypes.c_uint32), ctypes.c_int32]
+    lib.thin_topology_table.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+# ----------------------------------------------------------- C-named wrappers
+
+
+def thin_create(cfg: thin_config | None = None) -> ctypes.c_void_p:
+    lib = load_library()
+    h = ctypes.c_void_p()
+    rc = lib.thin_create(ctypes.byref(h), ctypes.byref(cfg) if cfg is not None else None)
+    if rc != THIN_OK:
+        raise ThinError(rc, "thin_create: " + thin_strerror(rc))
+    return h
+
+
+def thin_run(ctx, image_ptr: int, h: int, w: int, dtype: int, lam: int, adjacency: int,
+             stats: thin_stats | None = None) -> int:
+    return load_library().thin_run(ctx, ctypes.c_void_p(image_ptr), h, w, dtype,
+                                   ctypes.c_uint32(lam), adjacency,
+                                   ctypes.byref(stats) if stats is not None else None)
+
+
+def thin_run_batch(ctx, images, n: int, stats=None) -> int:
+    return load_library().thin_run_batch(ctx, images, n, stats)
+
+
+def thin_serve_admit(ctx, image: thin_image, tag: int) -> int:
+    return load_library().thin_serve_admit(ctx, ctypes.byref(image), ctypes.c_uint64(tag))
+
+
+def thin_serve_step(ctx, rounds: int, done_tags, done_stats, cap: int, n_done, n_resident) -> int:
+    return load_library().thin_serve_step(ctx, rounds, done_tags, done_stats, cap, n_done,
+                                          n_resident)
+
+
+def thin_destroy(ctx) -> int:
+    return load_library().thin_destroy(ctx)
+
+
+def thin_strerror(code: int) -> str:
+    return load_library().thin_strerror(code).decode()
+
+
+def thin_last_error(ctx) -> str:
+    return load_library().thin_last_error(ctx).decode()
+
+
+def thin_profile(ctx, reset: bool = False) -> thin_profile_info:
+    info = thin_profile_info()
+    rc = load_library().thin_profile(ctx, ctypes.byref(info), 1 if reset else 0)
+    if rc != THIN_OK:
+        raise ThinError(rc, "thin_profile")
+    return info
+
+
+def thin_topology_table(adjacency: int):
+    """The connectivity table the kernels use: a list of 256 (flags, comps)."""
+    lib = load_library()
+    buf = (ctypes.c_uint32 * 512)()
+    rc = lib.thin_topology_table(adjacency, buf, 512)
+    if rc != THIN_OK:
+        raise ThinError(rc, "thin_topology_table")
+    return [(buf[2 * m], buf[2 * m + 1]) for m in range(256)]
+
+
+# ------------------------------------------------------- tensor-level helpers
+
+
+@dataclass
+class Stats:
+    passes: int
+    lowerings: int
+    tile_rounds: int
+    converged: bool
+
+    @staticmethod
+    def of(s: thin_stats) -> "Stats":
+        return Stats(int(s.passes), int(s.lowerings), int(s.tile_rounds), bool(s.converged))
+
+
+def _adj_code(adj) -> int:
+    if adj in (THIN_ADJ_8_4, "8,4", (8, 4)):
+        return THIN_ADJ_8_4
+    if adj in (THIN_ADJ_4_8, "4,8", (4, 8)):
+        return THIN_ADJ_4_8
+    raise ValueError(f"unknown adjacency {adj!r}")
+
+
+def _dtype_code(t) -> int:
+    import torch
+
+    if t.dtype == torch.uint8:
+        return THIN_U8
+    if t.dtype == torch.uint16:
+        return THIN_U16
+    raise ValueError(f"unsupported dtype {t.dtype}")
+
+
+def describe(t, lam: int, adj) -> thin_image:
+    """thin_image for a 2-D uint8/uint16 CUDA tensor with unit column stride."""
+    if t.dim() != 2 or not t.is_cuda:
+        raise ValueError("expected a 2-D tensor on the GPU")
+    if t.numel() and t.stride(1) != 1:
+        raise ValueError("columns must be contiguous")
+    im = thin_image()
+    im.image = t.data_ptr() if t.numel() else None
+    im.h, im.w = int(t.shape[0]), int(t.shape[1])
+    im.pitch_elems = int(t.stride(0)) if t.numel() else int(t.shape[1])
+    im.dtype = _dtype_code(t)
+    im.lambda_ = int(lam)
+    im.adjacency = _adj_code(adj)
+    return im
+
+
+class Context:
+    """Owns a thin_ctx bound to a device and a stream (torch's current stream
+    of that device when not given)."""
+
+    def __init__(self, device: int = 0, stream=None, engine: int = THIN_ENGINE_AUTO,
+                 max_device_bytes: int = 0, max_passes: int = 0, tile: int = 0,
+                 steps_per_round: int = 0, profile: bool = False):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        cfg = thin_config()
+        cfg.device = device
+        cfg.engine = engine
+        cfg.hip_stream = stream.cuda_stream or None
+        cfg.max_device_bytes = max_device_bytes
+        cfg.max_passes = max_passes
+        cfg.tile = tile
+        cfg.steps_per_round = steps_per_round
+        cfg.flags = THIN_FLAG_PROFILE if profile else 0
+        self.device = device
+        self.stream = stream
+        self.handle = thin_create(cfg)
+
+    def close(self):
+        if self.handle:
+            thin_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, what: str, allow_limit: bool = False):
+        if rc == THIN_OK or (allow_limit and rc == THIN_ELIMIT):
+            return
+        raise ThinError(rc, f"{what}: {thin_strerror(rc)}: {thin_last_error(self.handle)}")
+
+    def profile(self, reset: bool = False) -> thin_profile_info:
+        return thin_profile(self.handle, reset)
+
+    def run(self, t, lam: int, adj="8,4", allow_limit: bool = False) -> Stats:
+        """Thins one device tensor in place; returns its statistics."""
+        im = describe(t, lam, adj)
+        st = thin_stats()
+        rc = load_library().thin_run_batch(self.handle, ctypes.byref(im), 1, ctypes.byref(st))
+        self._check(rc, "thin_run", allow_limit)
+        return Stats.of(st)
+
+    def run_batch(self, tensors, lams, adjs, allow_limit: bool = False):
+        n = len(tensors)
+        arr = (thin_image * max(n, 1))()
+        for i, (t, lam, adj) in enumerate(zip(tensors, lams, adjs)):
+            arr[i] = describe(t, lam, adj)
+        st = (thin_stats * max(n, 1))()
+        rc = thin_run_batch(self.handle, arr, n, st)
+        self._check(rc, "thin_run_batch", allow_limit)
+        return [Stats.of(st[i]) for i in range(n)]
+
+
+def run(t, lam: int, adj="8,4", **kw) -> Stats:
+    """One-shot convenience: thin device tensor `t` in place."""
+    with Context(device=t.device.index or 0, **kw) as ctx:
+        return ctx.run(t, lam, adj)

@@ -1,0 +1,176 @@
+"""GPU parity: the HIP path against the CPU oracle, bit for bit (image, pass
+count and lowering count), through the C ABI.
+
+Sizes are chosen so the oracle finishes in seconds while still spanning
+several tiles with ragged right and bottom edges; the degenerate sizes, both
+dtypes, both adjacency pairs and lambda from 0 to 2^32-1 are covered.  The
+oracle side uses ORACLE-SWEEP-DIRTY, which the CPU suite pins equal to the
+plain sweep.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1603_09180_amd import synth, thin
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SHAPES = [(32, 32, 8), (32, 32, 16), (64, 64, 16), (64, 64, 32)]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_thin(F, lam, adj, **kw):
+    t = torch.from_numpy(np.ascontiguousarray(F)).cuda()
+    with thin.Context(**kw) as ctx:
+        st = ctx.run(t, lam, adj, allow_limit=bool(kw.get("max_passes")))
+    torch.cuda.synchronize()
+    return t.cpu().numpy(), st
+
+
+def assert_same(F, lam, adj, got, st, ref=None):
+    if ref is None:
+        ref = oracle.sweep_dirty(F, lam, adj)
+    bad = np.argwhere(got != ref.image)
+    assert bad.size == 0, f"{len(bad)} pixels differ, first at {bad[:5].tolist()}"
+    assert (st.passes, st.lowerings) == (ref.passes, ref.lowerings)
+    assert st.converged
+
+
+@pytest.mark.parametrize("engine", [thin.THIN_ENGINE_TILED, thin.THIN_ENGINE_STEP])
+def test_blobs_128_lambda0(engine):
+    job = synth.blobs_128()
+    F = job.image()
+    say("case blobs_128 engine", engine)
+    got, st = gpu_thin(F, job.lam, job.adj, engine=engine)
+    assert_same(F, job.lam, job.adj, got, st)
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "t%dk%d" % (s[0], s[2]))
+def test_blobs_128_every_tile_shape(shape):
+    job = synth.blobs_128()
+    F = job.image()
+    say("case blobs_128 shape", shape)
+    got, st = gpu_thin(F, job.lam, job.adj, tile=shape[0], steps_per_round=shape[2])
+    assert_same(F, job.lam, job.adj, got, st)
+
+
+def test_ridges_512_lambda20():
+    job = synth.ridges_512()
+    F = job.image()
+    say("case ridges_512")
+    got, st = gpu_thin(F, job.lam, job.adj)
+    assert_same(F, job.lam, job.adj, got, st)
+
+
+def _fuzz_cases():
+    rng = np.random.default_rng(2024)
+    sides = [3, 4, 5, 7, 31, 32, 33, 63, 64, 65, 96, 97, 129, 200, 257, 300]
+    lams = [0, 1, 5, 20, 50, 500, 2**32 - 1]
+    cases = []
+    for k in range(48):
+        h = int(rng.choice(sides))
+        w = int(rng.choice(sides))
+        dt = np.uint8 if k % 2 == 0 else np.uint16
+        adj = int(rng.integers(0, 2))
+        lam = int(rng.choice(lams))
+        if dt == np.uint8 and lam == 500:
+            lam = 50
+        cases.append((k, h, w, dt, adj, lam))
+    return cases
+
+
+@pytest.mark.parametrize("case", _fuzz_cases(), ids=lambda c: "c%d_%dx%d_%s_a%d_l%d" % (
+    c[0], c[1], c[2], np.dtype(c[3]).name, c[4], c[5]))
+def test_fuzz(case):
+    k, h, w, dt, adj, lam = case
+    F = synth.gen_blobs(h, w, 7000 + k, dt, nblobs=6, sigma=(2.0, 12.0), noise=12.0)
+    say("case fuzz", case)
+    got, st = gpu_thin(F, lam, adj)
+    assert_same(F, lam, adj, got, st)
+
+
+def test_schedule_invariance_u16_4_8():
+    """Tile shape, halo width and engine change the schedule, never the bytes."""
+    F = synth.gen_blobs(150, 201, 77, np.uint16, nblobs=10, sigma=(3.0, 20.0))
+    ref = oracle.sweep_dirty(F, 500, 1)
+    for shape in SHAPES:
+        say("case invariance shape", shape)
+        got, st = gpu_thin(F, 500, 1, tile=shape[0], steps_per_round=shape[2])
+        assert_same(F, 500, 1, got, st, ref)
+    got, st = gpu_thin(F, 500, 1, engine=thin.THIN_ENGINE_STEP)
+    assert_same(F, 500, 1, got, st, ref)
+
+
+def test_batch_equals_oracle_per_image():
+    rng = np.random.default_rng(9)
+    Fs, lams, adjs = [], [], []
+    for i in range(14):
+        h, w = int(rng.integers(3, 180)), int(rng.integers(3, 180))
+        dt = np.uint8 if i % 3 else np.uint16
+        Fs.append(synth.gen_blobs(h, w, 9100 + i, dt, sigma=(2.0, 10.0)))
+        lams.append(int(rng.choice([0, 5, 20, 50])) * (257 if dt == np.uint16 else 1))
+        adjs.append(i % 2)
+    Fs.append(np.zeros((2, 50), np.uint8))      # no interior
+    lams.append(0)
+    adjs.append(0)
+    ts = [torch.from_numpy(F).cuda() for F in Fs]
+    say("case batch of", len(ts))
+    with thin.Context() as ctx:
+        sts = ctx.run_batch(ts, lams, adjs)
+    torch.cuda.synchronize()
+    for F, t, lam, adj, st in zip(Fs, ts, lams, adjs, sts):
+        if min(F.shape) < 3:
+            assert np.array_equal(t.cpu().numpy(), F) and st.passes == 0
+            continue
+        assert_same(F, lam, adj, t.cpu().numpy(), st)
+
+
+def test_pass_cap_then_resume():
+    F = synth.gen_blobs(90, 70, 123)
+    full = oracle.sweep(F, 0)
+    part = oracle.sweep(F, 0, max_passes=3)
+    assert part.limited
+    say("case pass cap")
+    t = torch.from_numpy(F.copy()).cuda()
+    with thin.Context(max_passes=3) as ctx:
+        st = ctx.run(t, 0, 0, allow_limit=True)
+        assert not st.converged and st.passes == 3 and st.lowerings == part.lowerings
+        assert np.array_equal(t.cpu().numpy(), part.image)
+    with thin.Context() as ctx:
+        st = ctx.run(t, 0, 0)
+    assert np.array_equal(t.cpu().numpy(), full.image)
+    assert st.lowerings + part.lowerings == full.lowerings
+
+
+def test_pitched_view_leaves_margin_untouched():
+    big = synth.gen_blobs(80, 140, 5)
+    F = big[:, 10:110].copy()
+    t_big = torch.from_numpy(big.copy()).cuda()
+    view = t_big[:, 10:110]
+    assert view.stride(0) == 140
+    say("case pitched")
+    with thin.Context() as ctx:
+        st = ctx.run(view, 0, 0)
+    out = t_big.cpu().numpy()
+    assert np.array_equal(out[:, :10], big[:, :10]) and np.array_equal(out[:, 110:], big[:, 110:])
+    assert_same(F, 0, 0, out[:, 10:110], st)
+
+
+@pytest.mark.parametrize("shape", [(0, 0), (1, 40), (2, 2), (40, 2), (3, 3)])
+def test_degenerate_sizes(shape):
+    F = (np.arange(int(np.prod(shape)), dtype=np.uint8).reshape(shape) * 37) % 251
+    say("case degenerate", shape)
+    with thin.Context() as ctx:
+        t = torch.from_numpy(F.copy()).cuda()
+        st = ctx.run(t, 0, 0)
+    ref = oracle.sweep(F, 0)
+    assert np.array_equal(t.cpu().numpy(), ref.image)
+    assert st.passes == ref.passes and st.lowerings == ref.lowerings
