@@ -91,7 +91,7 @@ def cpu_baseline(images, budget_s: float):
     return px / dt / 1e6, n, dt
 
 
-def bench_single(job, name, steps, warmup, cpu_s, tile, k):
+def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, profile=True):
     import numpy as np
     import torch
 
@@ -105,7 +105,7 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k):
     src = torch.from_numpy(F).cuda()
     inputs = [src.clone() for _ in range(warmup + steps)]
     torch.cuda.synchronize()
-    ctx = thin.Context(device=0, profile=True, tile=tile, steps_per_round=k)
+    ctx = thin.Context(device=0, profile=profile, tile=tile, steps_per_round=k, engine=engine)
     for i in range(warmup):
         ctx.run(inputs[i], job.lam, job.adj)
     torch.cuda.synchronize()
@@ -150,7 +150,8 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k):
         "data": "synthetic",
         "config": {"workload": name, "h": h, "w": w, "lambda": job.lam,
                    "adjacency": "8,4" if job.adj == 0 else "4,8", "images_per_step": 1,
-                   "path": "plain (thin_run)"},
+                   "path": "plain (thin_run)",
+                   "engine": {0: "auto", 1: "tiled", 2: "step", 3: "persistent", 4: "cooperative"}[engine]},
         "images_per_s": round(steps / elapsed, 2),
         "latency_ms_p50": round(_percentile(lat, 0.5), 4),
         "latency_ms_p99": round(_percentile(lat, 0.99), 4),
@@ -180,7 +181,7 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k):
     return out
 
 
-def bench_batch(steps, warmup, cpu_s, tile, k, n_images=512):
+def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512):
     import numpy as np
     import torch
 
@@ -193,7 +194,7 @@ def bench_batch(steps, warmup, cpu_s, tile, k, n_images=512):
     srcs = [torch.from_numpy(F).cuda() for F in Fs]
     lams = [j.lam for j in jobs]
     adjs = [j.adj for j in jobs]
-    ctx = thin.Context(device=0, profile=True, tile=tile, steps_per_round=k)
+    ctx = thin.Context(device=0, profile=True, tile=tile, steps_per_round=k, engine=engine)
     sets = [[s.clone() for s in srcs] for _ in range(warmup + steps)]
     torch.cuda.synchronize()
     for i in range(warmup):
@@ -275,6 +276,10 @@ def main():
                     help="CPU budget of the oracle baseline (0 disables it)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--k", type=int, default=0)
+    ap.add_argument("--engine", type=int, default=0,
+                    help="0 auto, 1 tiled, 2 step, 3 persistent (disabled), 4 cooperative")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="time without per-launch HIP events (roofline fields become null)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -288,12 +293,13 @@ def main():
     from paper_1603_09180_amd import synth
 
     if args.workload == "batch_512":
-        out = bench_batch(args.steps, args.warmup, args.cpu_seconds, args.tile, args.k)
+        out = bench_batch(args.steps, args.warmup, args.cpu_seconds, args.tile, args.k,
+                          args.engine)
     else:
         job = {"ridges_512": synth.ridges_512, "blobs_128": synth.blobs_128,
                "blobs_8192_u16": synth.blobs_8192_u16}[args.workload]()
         out = bench_single(job, args.workload, args.steps, args.warmup, args.cpu_seconds,
-                           args.tile, args.k)
+                           args.tile, args.k, args.engine, not args.no_profile)
     print(json.dumps(out), flush=True)
 
 

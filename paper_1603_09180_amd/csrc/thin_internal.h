@@ -22,6 +22,8 @@ struct ImgDev {
     int32_t tile0;       // index of its first tile in the launch's tile arrays
     int32_t round0;      // launch round at which the image's step 0 starts
     int32_t max_steps;   // parity-step cap (4 * max_passes), INT32_MAX if none
+    int32_t ring0;       // persistent engine: first entry of its round-completion ring
+    int32_t ring_w;      // ring length (> largest round spread between its tiles)
 };
 
 // Per-image counters, written by the kernels with device-scope atomics.
@@ -29,7 +31,14 @@ struct ImgCnt {
     unsigned long long lowerings;
     unsigned long long tile_rounds;
     int32_t last_step;   // image-local index of the last step that lowered, -1 if none
-    int32_t pad;
+    int32_t final_round; // persistent engine: rounds after which the image is final, -1 before
+};
+
+// Scheduler state of one persistent launch.
+struct Sched {
+    unsigned long long next;   // work items handed out (item q = round q / ntiles, tile q % ntiles)
+    int32_t images_left;       // images not yet final
+    int32_t error;             // 1 when a dependency wait exceeded its time limit
 };
 
 // Connectivity table entry for an upper-neighbour mask (see thin_topology_table).
@@ -56,6 +65,20 @@ hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs,
                         const TopoEntry* lut, int grid_blocks);
 hipError_t launch_step(hipStream_t stream, const ImgDev* img_host, const ImgDev* img_dev,
                        ImgCnt* cnt, int step, const TopoEntry* lut);
+hipError_t launch_persist(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
+                          const int32_t* tile_img, int32_t* tile_last, int32_t* progress,
+                          int32_t* ring, Sched* sched, int ntiles, const TopoEntry* lut,
+                          int grid_blocks, unsigned long long wait_ticks,
+                          unsigned long long kernel_ticks);
+hipError_t launch_coop(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
+                       const int32_t* tile_img, int32_t* tile_last, int ntiles,
+                       const TopoEntry* lut, int32_t* active, int32_t* rounds_out,
+                       int max_rounds, int num_cus);
+hipError_t launch_init_persist(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t* tile_last,
+                               int32_t* progress, int ntiles, int32_t* ring, int nring,
+                               Sched* sched);
+int persist_threads(TileShape s);
+int persist_blocks_per_cu(TileShape s);
 bool tile_shape_supported(TileShape s);
 int round_blocks_per_cu(TileShape s);
 

@@ -29,6 +29,8 @@
 
 #include <climits>
 
+#include <hip/hip_cooperative_groups.h>
+
 namespace thin {
 
 namespace {
@@ -45,21 +47,22 @@ __device__ __forceinline__ bool decide(uint32_t v, const uint32_t (&nb)[8], cons
     for (int p = 0; p < 8; ++p) u |= (uint32_t)(nb[p] >= v) << p;
     const TopoEntry e = lut[u];
     bool lower = (e.flags & 1u) != 0u;
-    if (!lower && lambda != 0u) {
-        const uint32_t k = (e.flags >> 4) & 7u;
-        if (k >= 2u) {
-            uint32_t q = 0;  // lower neighbours within lambda of v
+    const uint32_t k = (e.flags >> 4) & 7u;  // T--
+    if (!lower && lambda != 0u && k >= 2u) {
+        // lower neighbours y with v - F(y) <= lambda, i.e. F(y) >= v - lambda
+        const uint32_t floor_v = v > lambda ? v - lambda : 0u;
+        uint32_t q = 0;
 #pragma unroll
-            for (int p = 0; p < 8; ++p) q |= (uint32_t)(nb[p] < v && v - nb[p] <= lambda) << p;
-            const uint32_t hit = e.comps & (q * 0x01010101u);
-            const uint32_t nonzero = (((hit & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | hit) & 0x80808080u;
-            lower = (uint32_t)__popc(nonzero) + 1u >= k;
-        }
+        for (int p = 0; p < 8; ++p) q |= (uint32_t)(nb[p] >= floor_v) << p;
+        q &= ~u;
+        const uint32_t hit = e.comps & (q * 0x01010101u);
+        const uint32_t nonzero = (((hit & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | hit) & 0x80808080u;
+        lower = (uint32_t)__popc(nonzero) + 1u >= k;
     }
     if (lower) {
         uint32_t a = 0;
 #pragma unroll
-        for (int p = 0; p < 8; ++p) a = max(a, nb[p] < v ? nb[p] : 0u);
+        for (int p = 0; p < 8; ++p) a = max(a, ((u >> p) & 1u) ? 0u : nb[p]);
         alpha = a;
     }
     return lower;
@@ -86,7 +89,7 @@ __global__ void k_init_state(ImgCnt* cnt, int nimg, int32_t* tile_last, int ntil
         cnt[i].lowerings = 0ull;
         cnt[i].tile_rounds = 0ull;
         cnt[i].last_step = -1;
-        cnt[i].pad = 0;
+        cnt[i].final_round = -1;
     }
     if (i < ntiles) tile_last[i] = -1;
 }
@@ -124,105 +127,119 @@ __global__ __launch_bounds__(kThreads) void k_step(const ImgDev* __restrict__ im
     }
 }
 
-// ----------------------------------------------------------------- k_round
+// ------------------------------------------------------------ tile residency
 
-template <int TH, int TW, int K>
-struct RoundGeom {
+// Scalar fields of an image used inside a residency (no arrays, so the
+// compiler keeps them in registers).
+struct View {
+    int64_t pitch;
+    int32_t h, w;
+    int32_t dtype;
+    uint32_t lambda;
+};
+
+__device__ __forceinline__ View view_of(const ImgDev* d)
+{
+    View v;
+    v.pitch = d->pitch;
+    v.h = d->h;
+    v.w = d->w;
+    v.dtype = d->dtype;
+    v.lambda = d->lambda;
+    return v;
+}
+
+// Ping-pong buffer read by round r (src) and written by it (dst).  The
+// descriptor stays in global memory: copying it into a local and indexing its
+// array by r & 1 would push the copy into scratch.
+__device__ __forceinline__ const void* round_src(const ImgDev* d, int r)
+{
+    return d->buf[r & 1];
+}
+
+__device__ __forceinline__ void* round_dst(const ImgDev* d, int r)
+{
+    return d->buf[(r + 1) & 1];
+}
+
+// Geometry of a tile residency: a TH x TW interior plus a K-pixel halo,
+// staged in LDS as u16, processed by NT threads.
+template <int TH, int TW, int K, int NT>
+struct Tile {
     static constexpr int RH = TH + 2 * K;
     static constexpr int RW = TW + 2 * K;
     static constexpr int RWP = RW;  // LDS row pitch in elements
     // lanes across a candidate row: next power of two >= RW/2, at most 64
     static constexpr int LW = (RW / 2 <= 8) ? 8 : (RW / 2 <= 16) ? 16 : (RW / 2 <= 32) ? 32 : 64;
     static_assert(K <= TH && K <= TW, "halo must not exceed the tile side");
-};
+    static_assert(NT % LW == 0, "thread count must cover whole candidate rows");
 
-template <int TH, int TW, int K>
-__global__ __launch_bounds__(kThreads) void k_round(const ImgDev* __restrict__ imgs,
-                                                    ImgCnt* cnt,
-                                                    const int32_t* __restrict__ tile_img,
-                                                    int32_t* tile_last, int ntiles, int round,
-                                                    const TopoEntry* __restrict__ lut_g)
-{
-    using G = RoundGeom<TH, TW, K>;
-    constexpr int RH = G::RH, RW = G::RW, RWP = G::RWP, LW = G::LW;
-    __shared__ uint16_t s_img[RH * RWP];
-    __shared__ TopoEntry s_lut[512];
-    __shared__ int s_count;
-
-    const int tid = threadIdx.x;
-    for (int i = tid; i < 512; i += kThreads) s_lut[i] = lut_g[i];
-
-    for (int g = blockIdx.x; g < ntiles; g += gridDim.x) {
-        const int ii = tile_img[g];
-        const ImgDev d = imgs[ii];
-        const int r = round - d.round0;
-        if (r < 0) continue;
-        const int t0 = r * K;
-        const int nsteps = min(K, d.max_steps - t0);
-        if (nsteps <= 0) continue;
-        const int lt = g - d.tile0;
-        const int ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
-
-        // Neighbouring tiles of this round may update their tile_last while
-        // it is read here (values only grow, which can only add work), so one
-        // thread decides and the barrier broadcasts a block-uniform answer.
-        // The barrier also orders this tile's LDS writes after the previous
-        // tile's readers.
-        int vote = 0;
-        if (tid == 0) {
-            int32_t m = INT_MIN;
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int y = ty + dy;
-                if (y < 0 || y >= d.tiles_y) continue;
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int x = tx + dx;
-                    if (x < 0 || x >= d.tiles_x) continue;
-                    m = max(m, tile_last[d.tile0 + y * d.tiles_x + x]);
-                }
-            }
-            vote = (r == 0 || m >= t0 - 4) ? 1 : 0;
-        }
-        const bool active = __syncthreads_or(vote) != 0;
-        const int32_t own_last = tile_last[g];  // written only by this block
-
-        const void* src = d.buf[r & 1];
-        void* dst = d.buf[(r + 1) & 1];
-        const int gy0 = ty * TH, gx0 = tx * TW;  // tile interior origin
+    // Interior copy src -> dst (a stable tile keeping the ping-pong pair equal).
+    static __device__ void copy_interior(const View d, int gy0, int gx0, const void* src,
+                                         void* dst, int tid)
+    {
         const int ih = min(TH, d.h - gy0), iw = min(TW, d.w - gx0);
-
-        if (!active) {
-            // Stable for this round.  The output buffer already equals the
-            // input unless the tile changed during the previous round.
-            if (own_last >= t0 - K) {
-                for (int idx = tid; idx < TH * TW; idx += kThreads) {
-                    const int y = idx / TW, x = idx - y * TW;
-                    if (y < ih && x < iw) {
-                        const int64_t o = (int64_t)(gy0 + y) * d.pitch + (gx0 + x);
-                        store_px(dst, d.dtype, o, load_px(src, d.dtype, o));
-                    }
-                }
+        for (int idx = tid; idx < TH * TW; idx += NT) {
+            const int y = idx / TW, x = idx - y * TW;
+            if (y < ih && x < iw) {
+                const int64_t o = (int64_t)(gy0 + y) * d.pitch + (gx0 + x);
+                store_px(dst, d.dtype, o, load_px(src, d.dtype, o));
             }
-            continue;
         }
+    }
 
-        // Stage the tile and its K-pixel halo (zeros outside the image; they
-        // are never read by a candidate, whose 3x3 lies inside the image).
+    // Stages the tile and its halo from src, runs nsteps parity steps starting
+    // at image step t0, writes the interior to dst.  Returns the number of
+    // interior lowerings (same value in every thread) and, in last_tau
+    // (block-uniform), the last step index within the residency that lowered
+    // an interior pixel (-1 if none).  Must be entered by all NT threads after
+    // a barrier that ends the previous use of the shared arrays.
+    //
+    // A candidate is examined only when its 3x3 neighbourhood may have
+    // changed since it was last examined (re-examination rule of section
+    // 2.2): s_dirty starts at 1 everywhere (no history at staging), a
+    // candidate clears its flag when examined, and a lowered pixel marks its
+    // whole 3x3.  The decision is a function of the 3x3 only, so skipping
+    // clean candidates changes nothing.  Within a step no candidate reads or
+    // writes another candidate's flag: the 8 neighbours of a candidate belong
+    // to other parity classes.
+    static __device__ int run(const View d, int gy0, int gx0, int t0, int nsteps,
+                              const void* src, void* dst, uint16_t* s_img, uint8_t* s_dirty,
+                              const TopoEntry* lut, int* s_count, int* s_last, int tid,
+                              int& last_tau)
+    {
         const int ry0 = gy0 - K, rx0 = gx0 - K;
-        if (tid == 0) s_count = 0;
-        for (int idx = tid; idx < RH * RW; idx += kThreads) {
+        if (tid == 0) {
+            *s_count = 0;
+            *s_last = -1;
+        }
+        // All global loads of the region are issued before the first one is
+        // waited for.  Zeros outside the image are never read by a candidate:
+        // every candidate is an interior pixel whose 3x3 lies inside the image.
+        constexpr int ITER = (RH * RW + NT - 1) / NT;
+        uint32_t vals[ITER];
+#pragma unroll
+        for (int k = 0; k < ITER; ++k) {
+            const int idx = tid + k * NT;
             const int y = idx / RW, x = idx - y * RW;
             const int gi = ry0 + y, gj = rx0 + x;
-            uint32_t v = 0;
-            if (gi >= 0 && gi < d.h && gj >= 0 && gj < d.w)
-                v = load_px(src, d.dtype, (int64_t)gi * d.pitch + gj);
-            s_img[y * RWP + x] = (uint16_t)v;
+            vals[k] = 0;
+            if (idx < RH * RW && gi >= 0 && gi < d.h && gj >= 0 && gj < d.w)
+                vals[k] = load_px(src, d.dtype, (int64_t)gi * d.pitch + gj);
+        }
+#pragma unroll
+        for (int k = 0; k < ITER; ++k) {
+            const int idx = tid + k * NT;
+            const int y = idx / RW, x = idx - y * RW;
+            if (idx < RH * RW) {
+                s_img[y * RWP + x] = (uint16_t)vals[k];
+                s_dirty[y * RWP + x] = 1;
+            }
         }
         __syncthreads();
 
-        const TopoEntry* lut = s_lut + d.adj * 256;
         const uint32_t lambda = d.lambda;
         int my_count = 0;
-        int last_tau = -1;
         for (int tau = 0; tau < nsteps; ++tau) {
             const int s = (t0 + tau) & 3, si = s >> 1, sj = s & 1;
             // Exact region after tau steps, clipped to the image interior.
@@ -233,17 +250,24 @@ __global__ __launch_bounds__(kThreads) void k_round(const ImgDev* __restrict__ i
             const int na = r_hi >= r_first ? (r_hi - r_first) / 2 + 1 : 0;
             const int nb = c_hi >= c_first ? (c_hi - c_first) / 2 + 1 : 0;
             bool inner = false;
-            for (int a = tid / LW; a < na; a += kThreads / LW) {
+            for (int a = tid / LW; a < na; a += NT / LW) {
                 const int lr = r_first + 2 * a;
                 for (int b = tid % LW; b < nb; b += LW) {
                     const int lc = c_first + 2 * b;
-                    uint16_t* p = s_img + lr * RWP + lc;
+                    const int o = lr * RWP + lc;
+                    if (!s_dirty[o]) continue;
+                    s_dirty[o] = 0;
+                    uint16_t* p = s_img + o;
                     const uint32_t v = p[0];
                     const uint32_t nbv[8] = {p[1], p[-RWP + 1], p[-RWP], p[-RWP - 1],
                                              p[-1], p[RWP - 1], p[RWP], p[RWP + 1]};
                     uint32_t alpha;
                     if (decide(v, nbv, lut, lambda, alpha)) {
                         p[0] = (uint16_t)alpha;
+                        uint8_t* q = s_dirty + o;
+                        q[-RWP - 1] = 1; q[-RWP] = 1; q[-RWP + 1] = 1;
+                        q[-1] = 1;       q[0] = 1;    q[1] = 1;
+                        q[RWP - 1] = 1;  q[RWP] = 1;  q[RWP + 1] = 1;
                         if (lr >= K && lr < K + TH && lc >= K && lc < K + TW) {
                             ++my_count;
                             inner = true;
@@ -251,36 +275,402 @@ __global__ __launch_bounds__(kThreads) void k_round(const ImgDev* __restrict__ i
                     }
                 }
             }
-            if (__syncthreads_or(inner)) last_tau = tau;
+            // One lane per wave that lowered an interior pixel records the step.
+            if (__ballot(inner) != 0ull && (tid & 63) == 0) atomicMax(s_last, tau);
+            __syncthreads();
         }
 
-        for (int idx = tid; idx < TH * TW; idx += kThreads) {
+        const int ih = min(TH, d.h - gy0), iw = min(TW, d.w - gx0);
+        for (int idx = tid; idx < TH * TW; idx += NT) {
             const int y = idx / TW, x = idx - y * TW;
             if (y < ih && x < iw)
                 store_px(dst, d.dtype, (int64_t)(gy0 + y) * d.pitch + (gx0 + x),
                          s_img[(K + y) * RWP + (K + x)]);
         }
-        if (my_count) atomicAdd(&s_count, my_count);
+        if (my_count) atomicAdd(s_count, my_count);
         __syncthreads();
-        if (tid == 0) {
-            atomicAdd(&cnt[ii].tile_rounds, 1ull);
-            if (last_tau >= 0) {
-                tile_last[g] = t0 + last_tau;
-                atomicAdd(&cnt[ii].lowerings, (unsigned long long)s_count);
-                atomicMax(&cnt[ii].last_step, t0 + last_tau);
-            }
+        last_tau = *s_last;
+        return *s_count;
+    }
+};
+
+// Largest tile_last over the 3x3 tile neighbourhood of (ty, tx).
+__device__ __forceinline__ int32_t neighbourhood_last(const ImgDev* d, const int32_t* tile_last,
+                                                      int ty, int tx)
+{
+    const int tiles_x = d->tiles_x, tiles_y = d->tiles_y, tile0 = d->tile0;
+    int32_t m = INT_MIN;
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int y = ty + dy;
+        if (y < 0 || y >= tiles_y) continue;
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int x = tx + dx;
+            if (x < 0 || x >= tiles_x) continue;
+            m = max(m, __hip_atomic_load(&tile_last[tile0 + y * tiles_x + x], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT));
         }
     }
+    return m;
 }
 
-template <int TH, int TW, int K>
+// ----------------------------------------------------------------- k_round
+
+// One tile of one round (launch-per-round and cooperative engines).
+// Returns 1 when the tile was processed (active), 0 when skipped.  All NT
+// threads must call it together.
+template <int TH, int TW, int K, int NT>
+__device__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
+                          const int32_t* __restrict__ tile_img, int32_t* tile_last, int g,
+                          int round, uint16_t* s_img, uint8_t* s_dirty, const TopoEntry* s_lut,
+                          int* s_count, int* s_last)
+{
+    using T = Tile<TH, TW, K, NT>;
+    const int tid = threadIdx.x;
+    const int ii = tile_img[g];
+    const ImgDev* d = imgs + ii;
+    const int r = round - d->round0;
+    if (r < 0) return 0;
+    const int t0 = r * K;
+    const int nsteps = min(K, d->max_steps - t0);
+    if (nsteps <= 0) return 0;
+    const int lt = g - d->tile0;
+    const int ty = lt / d->tiles_x, tx = lt - ty * d->tiles_x;
+
+    // Neighbouring tiles of this round may update their tile_last while it
+    // is read here (values only grow, which can only add work), so one thread
+    // decides and the barrier broadcasts a block-uniform answer.  The barrier
+    // also orders this tile's LDS writes after the previous tile's readers.
+    int vote = 0;
+    if (tid == 0) vote = (r == 0 || neighbourhood_last(d, tile_last, ty, tx) >= t0 - 4) ? 1 : 0;
+    const bool active = __syncthreads_or(vote) != 0;
+    const int32_t own_last = tile_last[g];  // written only by this tile's residencies
+    const void* src = round_src(d, r);
+    void* dst = round_dst(d, r);
+    const int gy0 = ty * TH, gx0 = tx * TW;
+    const View v = view_of(d);
+
+    if (!active) {
+        // Stable for this round.  The output buffer already equals the input
+        // unless the tile changed during the previous round.
+        if (own_last >= t0 - K) T::copy_interior(v, gy0, gx0, src, dst, tid);
+        return 0;
+    }
+    int last_tau;
+    const int count = T::run(v, gy0, gx0, t0, nsteps, src, dst, s_img, s_dirty,
+                             s_lut + d->adj * 256, s_count, s_last, tid, last_tau);
+    if (tid == 0) {
+        atomicAdd(&cnt[ii].tile_rounds, 1ull);
+        if (last_tau >= 0) {
+            __hip_atomic_store(&tile_last[g], t0 + last_tau, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            atomicAdd(&cnt[ii].lowerings, (unsigned long long)count);
+            atomicMax(&cnt[ii].last_step, t0 + last_tau);
+        }
+    }
+    return 1;
+}
+
+template <int TH, int TW, int K, int NT>
+__global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
+                                              const int32_t* __restrict__ tile_img,
+                                              int32_t* tile_last, int ntiles, int round,
+                                              const TopoEntry* __restrict__ lut_g)
+{
+    using T = Tile<TH, TW, K, NT>;
+    __shared__ uint16_t s_img[T::RH * T::RWP];
+    __shared__ uint8_t s_dirty[T::RH * T::RWP];
+    __shared__ TopoEntry s_lut[512];
+    __shared__ int s_count, s_last;
+    for (int i = threadIdx.x; i < 512; i += NT) s_lut[i] = lut_g[i];
+    for (int g = blockIdx.x; g < ntiles; g += gridDim.x)
+        round_tile<TH, TW, K, NT>(imgs, cnt, tile_img, tile_last, g, round, s_img, s_dirty, s_lut,
+                                  &s_count, &s_last);
+}
+
+// ------------------------------------------------------------------ k_coop
+//
+// All rounds in one cooperative launch (every block resident): each round
+// processes the tile list like k_round, then the whole grid synchronises.
+// active[round % 3] counts the tiles processed in a round; a round in which
+// no tile was active means every image is stable (a tile is skipped only when
+// its neighbourhood was quiet for the last 4 steps), so all blocks leave
+// together.  The counter of round r is read by every block right after the
+// grid barrier of round r and is cleared during round r + 2, after the next
+// barrier has proved those reads complete.
+
+template <int TH, int TW, int K, int NT>
+__global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
+                                             const int32_t* __restrict__ tile_img,
+                                             int32_t* tile_last, int ntiles,
+                                             const TopoEntry* __restrict__ lut_g, int32_t* active,
+                                             int32_t* rounds_out, int max_rounds)
+{
+    using T = Tile<TH, TW, K, NT>;
+    __shared__ uint16_t s_img[T::RH * T::RWP];
+    __shared__ uint8_t s_dirty[T::RH * T::RWP];
+    __shared__ TopoEntry s_lut[512];
+    __shared__ int s_count, s_last;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 512; i += NT) s_lut[i] = lut_g[i];
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    int round = 0;
+    for (;; ++round) {
+        if (blockIdx.x == 0 && tid == 0)
+            __hip_atomic_store(&active[(round + 1) % 3], 0, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        int mine = 0;
+        for (int g = blockIdx.x; g < ntiles; g += gridDim.x)
+            mine += round_tile<TH, TW, K, NT>(imgs, cnt, tile_img, tile_last, g, round, s_img,
+                                              s_dirty, s_lut, &s_count, &s_last);
+        if (tid == 0 && mine) atomicAdd(&active[round % 3], mine);
+        // Stores of every wave must be acknowledged before the grid barrier
+        // publishes them.
+        __builtin_amdgcn_s_waitcnt(0);
+        grid.sync();
+        const int a = __hip_atomic_load(&active[round % 3], __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+        if (a == 0 || round + 1 >= max_rounds) break;
+    }
+    if (blockIdx.x == 0 && tid == 0) *rounds_out = round + 1;
+}
+
+template <int TH, int TW, int K, int NT>
+hipError_t launch_coop_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
+                         const int32_t* tile_img, int32_t* tile_last, int ntiles,
+                         const TopoEntry* lut, int32_t* active, int32_t* rounds_out,
+                         int max_rounds, int num_cus)
+{
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT>), NT, 0);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    const int grid = max(1, min(ntiles, per_cu * num_cus));
+    void* args[] = {(void*)&imgs,   (void*)&cnt,    (void*)&tile_img,   (void*)&tile_last,
+                    (void*)&ntiles, (void*)&lut,    (void*)&active,     (void*)&rounds_out,
+                    (void*)&max_rounds};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT>),
+                                      dim3(grid), dim3(NT), args, 0, stream);
+}
+
+template <int TH, int TW, int K, int NT>
 hipError_t launch_round_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                           const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
                           const TopoEntry* lut, int grid_blocks)
 {
     const int grid = max(1, min(ntiles, grid_blocks));
-    hipLaunchKernelGGL((k_round<TH, TW, K>), dim3(grid), dim3(kThreads), 0, stream, imgs, cnt,
+    hipLaunchKernelGGL((k_round<TH, TW, K, NT>), dim3(grid), dim3(NT), 0, stream, imgs, cnt,
                        tile_img, tile_last, ntiles, round, lut);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- k_persist
+//
+// One launch runs every image of the work list to stability.  Work item q is
+// (round r = q / ntiles, tile g = q % ntiles); items are handed out in order
+// by one atomic counter.  Item (r, g) may start once tile g and its 8
+// neighbouring tiles have completed round r - 1.  Those items were handed out
+// earlier, to blocks that are running, and the oldest item still outstanding
+// never waits, so the queue always drains; no co-residency is assumed.
+// Publishing a round: every thread fences its stores at device scope, then
+// one thread raises progress[g] with release semantics; a waiter observes it
+// with acquire semantics before the block reads the halo.
+// Convergence: per image, a ring of per-round completion counters finds the
+// last tile to finish round r; that tile finalises the image when nothing
+// was lowered during the last 4 steps of round r (or the step cap is
+// reached).  Ring entries are reused after `ring_w` rounds, more than the
+// largest round spread between two tiles of one image (a tile is at most one
+// round ahead of each neighbour).  Every wait has a time limit, and so has
+// the whole launch: on expiry the block raises sched->error and all blocks
+// leave, so every wave reaches the end of the kernel.
+
+// Reads a word other blocks update, as a read-modify-write at device scope.
+// A plain relaxed load may be served from this XCD's L2, which is not kept
+// coherent with the other XCDs' L2s, so a polling loop could keep reading a
+// stale copy; an atomic RMW is performed at the device coherence point and
+// returns the latest value without invalidating any cache.
+__device__ __forceinline__ int ld_sync(int32_t* p)
+{
+    return __hip_atomic_fetch_add(p, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int TH, int TW, int K, int NT>
+__global__ __launch_bounds__(NT) void k_persist(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
+                                                const int32_t* __restrict__ tile_img,
+                                                int32_t* tile_last, int32_t* progress,
+                                                int32_t* ring, Sched* sched, int ntiles,
+                                                const TopoEntry* __restrict__ lut_g,
+                                                unsigned long long wait_ticks,
+                                                unsigned long long kernel_ticks)
+{
+    using T = Tile<TH, TW, K, NT>;
+    __shared__ uint16_t s_img[T::RH * T::RWP];
+    __shared__ uint8_t s_dirty[T::RH * T::RWP];
+    __shared__ TopoEntry s_lut[512];
+    __shared__ int s_count, s_last;
+    __shared__ int s_item[4];  // tile, round, active, copy
+
+    const int tid = threadIdx.x;
+    for (int i = tid; i < 512; i += NT) s_lut[i] = lut_g[i];
+    const unsigned long long kernel_start = wall_clock64();
+
+    for (;;) {
+        if (tid == 0) {
+            int item_g = -1, item_r = 0, item_active = 0, item_copy = 0;
+            const unsigned long long since = wall_clock64();
+            for (;;) {
+                if (ld_sync(&sched->images_left) <= 0 || ld_sync(&sched->error)) break;
+                if (wall_clock64() - since > 2 * wait_ticks ||
+                    wall_clock64() - kernel_start > kernel_ticks) {
+                    // Items keep being skipped while an image stays unfinished:
+                    // give up rather than spin.
+                    __hip_atomic_store(&sched->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                const unsigned long long q = atomicAdd(&sched->next, 1ull);
+                const int r = (int)(q / (unsigned long long)ntiles);
+                const int g = (int)(q % (unsigned long long)ntiles);
+                const int ii = tile_img[g];
+                const ImgDev* d = imgs + ii;
+                const int64_t t0 = (int64_t)r * K;
+                if (t0 >= d->max_steps) continue;  // beyond the step cap
+                int fr = ld_sync(&cnt[ii].final_round);
+                if (fr >= 0 && r >= fr) continue;  // image already final
+                const int tiles_x = d->tiles_x, tiles_y = d->tiles_y, tile0 = d->tile0;
+                const int lt = g - tile0;
+                const int ty = lt / tiles_x, tx = lt - ty * tiles_x;
+                bool skip = false, failed = false;
+                const unsigned long long w0 = wall_clock64();
+                for (;;) {
+                    // Poll with device-scope RMW reads (no cache
+                    // invalidation); one acquire fence follows success.
+                    bool ready = ld_sync(&progress[g]) >= r;
+                    for (int dy = -1; dy <= 1 && ready; ++dy) {
+                        const int y = ty + dy;
+                        if (y < 0 || y >= tiles_y) continue;
+                        for (int dx = -1; dx <= 1 && ready; ++dx) {
+                            const int x = tx + dx;
+                            if (x < 0 || x >= tiles_x || (dx == 0 && dy == 0)) continue;
+                            ready = ld_sync(&progress[tile0 + y * tiles_x + x]) >= r;
+                        }
+                    }
+                    if (ready) {
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                        break;
+                    }
+                    fr = ld_sync(&cnt[ii].final_round);
+                    if (fr >= 0 && r >= fr) { skip = true; break; }
+                    if (ld_sync(&sched->error) || wall_clock64() - w0 > wait_ticks ||
+                        wall_clock64() - kernel_start > kernel_ticks) {
+                        failed = true;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                if (failed) {
+                    __hip_atomic_store(&sched->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                if (skip) continue;
+                item_g = g;
+                item_r = r;
+                item_active = (r == 0 || neighbourhood_last(d, tile_last, ty, tx) >= (int)t0 - 4);
+                item_copy = tile_last[g] >= (int)t0 - K;
+                break;
+            }
+            s_item[0] = item_g;
+            s_item[1] = item_r;
+            s_item[2] = item_active;
+            s_item[3] = item_copy;
+        }
+        __syncthreads();
+        const int g = s_item[0];
+        if (g < 0) break;
+        const int r = s_item[1];
+        const int ii = tile_img[g];
+        const ImgDev* d = imgs + ii;
+        const int t0 = r * K;
+        const int nsteps = min(K, d->max_steps - t0);
+        const int lt = g - d->tile0;
+        const int ty = lt / d->tiles_x, tx = lt - ty * d->tiles_x;
+        const void* src = round_src(d, r);
+        void* dst = round_dst(d, r);
+        const int gy0 = ty * TH, gx0 = tx * TW;
+        const View v = view_of(d);
+        int last_tau = -1, count = 0;
+        if (s_item[2]) {
+            count = T::run(v, gy0, gx0, t0, nsteps, src, dst, s_img, s_dirty, s_lut + d->adj * 256,
+                           &s_count, &s_last, tid, last_tau);
+        } else if (s_item[3]) {
+            T::copy_interior(v, gy0, gx0, src, dst, tid);
+        }
+        // Publishing: each wave waits until its own stores are acknowledged
+        // (a workgroup barrier alone does not wait for them), then one
+        // thread's release fence writes the L2 back for other XCDs.
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) {
+            if (s_item[2]) atomicAdd(&cnt[ii].tile_rounds, 1ull);
+            if (last_tau >= 0) {
+                __hip_atomic_store(&tile_last[g], t0 + last_tau, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                atomicAdd(&cnt[ii].lowerings, (unsigned long long)count);
+                atomicMax(&cnt[ii].last_step, t0 + last_tau);
+            }
+            __hip_atomic_store(&progress[g], r + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const int slot = d->ring0 + r % d->ring_w;
+            const int done = __hip_atomic_fetch_add(&ring[slot], 1, __ATOMIC_ACQ_REL,
+                                                    __HIP_MEMORY_SCOPE_AGENT) + 1;
+            if (done == d->tiles_x * d->tiles_y) {
+                // Last tile of round r: every tile's counters of rounds <= r
+                // are in.  Later rounds cannot lower anything if this one
+                // ended quiet, so last_step decides stability exactly.
+                __hip_atomic_store(&ring[slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int ls = ld_sync(&cnt[ii].last_step);
+                const int64_t steps = min((int64_t)(r + 1) * K, (int64_t)d->max_steps);
+                if ((int64_t)ls < steps - 4 || steps >= d->max_steps) {
+                    __hip_atomic_store(&cnt[ii].final_round, r + 1, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_fetch_add(&sched->images_left, -1, __ATOMIC_ACQ_REL,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+    }
+}
+
+__global__ void k_init_persist(ImgCnt* cnt, int nimg, int32_t* tile_last, int32_t* progress,
+                               int ntiles, int32_t* ring, int nring, Sched* sched)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nimg) {
+        cnt[i].lowerings = 0ull;
+        cnt[i].tile_rounds = 0ull;
+        cnt[i].last_step = -1;
+        cnt[i].final_round = -1;
+    }
+    if (i < ntiles) {
+        tile_last[i] = -1;
+        progress[i] = 0;
+    }
+    if (i < nring) ring[i] = 0;
+    if (i == 0) {
+        sched->next = 0ull;
+        sched->images_left = nimg;
+        sched->error = 0;
+    }
+}
+
+template <int TH, int TW, int K, int NT>
+hipError_t launch_persist_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
+                            const int32_t* tile_img, int32_t* tile_last, int32_t* progress,
+                            int32_t* ring, Sched* sched, int ntiles, const TopoEntry* lut,
+                            int grid_blocks, unsigned long long wait_ticks,
+                            unsigned long long kernel_ticks)
+{
+    hipLaunchKernelGGL((k_persist<TH, TW, K, NT>), dim3(max(1, grid_blocks)), dim3(NT), 0, stream,
+                       imgs, cnt, tile_img, tile_last, progress, ring, sched, ntiles, lut,
+                       wait_ticks, kernel_ticks);
     return hipGetLastError();
 }
 
@@ -310,39 +700,97 @@ hipError_t launch_step(hipStream_t stream, const ImgDev* img_host, const ImgDev*
     return hipGetLastError();
 }
 
-#define THIN_ROUND_SHAPES(X) \
-    X(32, 32, 8)             \
-    X(32, 32, 16)            \
-    X(64, 64, 16)            \
-    X(64, 64, 32)
+// Compiled tile shapes: (tile height, tile width, halo = steps per residency,
+// threads of the persistent kernel).
+#define THIN_SHAPES(X)   \
+    X(32, 32, 8, 512)    \
+    X(32, 32, 16, 1024)  \
+    X(64, 64, 16, 1024)  \
+    X(64, 64, 32, 1024)
 
 bool tile_shape_supported(TileShape s)
 {
-#define X(a, b, c) if (s.th == a && s.tw == b && s.k == c) return true;
-    THIN_ROUND_SHAPES(X)
+#define X(a, b, c, n) if (s.th == a && s.tw == b && s.k == c) return true;
+    THIN_SHAPES(X)
 #undef X
     return false;
 }
 
+int persist_threads(TileShape s)
+{
+#define X(a, b, c, n) if (s.th == a && s.tw == b && s.k == c) return n;
+    THIN_SHAPES(X)
+#undef X
+    return 0;
+}
+
+static int lds_bytes(TileShape s) { return (s.th + 2 * s.k) * (s.tw + 2 * s.k) * 3 + 4096 + 64; }
+
 int round_blocks_per_cu(TileShape s)
 {
-    // LDS per block: region of u16 plus the 4 KiB table; 160 KiB per CU.
-    const int lds = (s.th + 2 * s.k) * (s.tw + 2 * s.k) * 2 + 4096 + 64;
-    int by_lds = (160 * 1024) / lds;
-    return max(1, min(8, by_lds));
+    const int by_lds = (160 * 1024) / lds_bytes(s);
+    const int by_threads = 2048 / max(64, persist_threads(s));
+    return max(1, min(by_lds, by_threads));
+}
+
+int persist_blocks_per_cu(TileShape s)
+{
+    const int by_lds = (160 * 1024) / lds_bytes(s);
+    const int by_threads = 2048 / max(64, persist_threads(s));
+    return max(1, min(by_lds, by_threads));
 }
 
 hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                         const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
                         const TopoEntry* lut, int grid_blocks)
 {
-#define X(a, b, c)                                                                       \
+#define X(a, b, c, n)                                                                    \
     if (shape.th == a && shape.tw == b && shape.k == c)                                  \
-        return launch_round_t<a, b, c>(stream, imgs, cnt, tile_img, tile_last, ntiles,   \
-                                       round, lut, grid_blocks);
-    THIN_ROUND_SHAPES(X)
+        return launch_round_t<a, b, c, n>(stream, imgs, cnt, tile_img, tile_last, ntiles, \
+                                          round, lut, grid_blocks);
+    THIN_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_persist(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
+                          const int32_t* tile_img, int32_t* tile_last, int32_t* progress,
+                          int32_t* ring, Sched* sched, int ntiles, const TopoEntry* lut,
+                          int grid_blocks, unsigned long long wait_ticks,
+                          unsigned long long kernel_ticks)
+{
+#define X(a, b, c, n)                                                                        \
+    if (shape.th == a && shape.tw == b && shape.k == c)                                      \
+        return launch_persist_t<a, b, c, n>(stream, imgs, cnt, tile_img, tile_last, progress, \
+                                            ring, sched, ntiles, lut, grid_blocks, wait_ticks, \
+                                            kernel_ticks);
+    THIN_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_coop(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
+                       const int32_t* tile_img, int32_t* tile_last, int ntiles,
+                       const TopoEntry* lut, int32_t* active, int32_t* rounds_out,
+                       int max_rounds, int num_cus)
+{
+#define X(a, b, c, n)                                                                        \
+    if (shape.th == a && shape.tw == b && shape.k == c)                                      \
+        return launch_coop_t<a, b, c, n>(stream, imgs, cnt, tile_img, tile_last, ntiles, lut, \
+                                         active, rounds_out, max_rounds, num_cus);
+    THIN_SHAPES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_init_persist(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t* tile_last,
+                               int32_t* progress, int ntiles, int32_t* ring, int nring,
+                               Sched* sched)
+{
+    const int n = max(max(nimg, ntiles), max(nring, 1));
+    hipLaunchKernelGGL(k_init_persist, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
+                       stream, cnt, nimg, tile_last, progress, ntiles, ring, nring, sched);
+    return hipGetLastError();
 }
 
 }  // namespace thin

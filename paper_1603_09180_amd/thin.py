@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(HERE, "libthin.so")
 THIN_OK, THIN_EINVAL, THIN_ENOMEM, THIN_EDEVICE, THIN_ELIMIT, THIN_EBUSY = 0, -1, -2, -3, -4, -5
 THIN_U8, THIN_U16 = 1, 2
 THIN_ADJ_8_4, THIN_ADJ_4_8 = 0, 1
-THIN_ENGINE_AUTO, THIN_ENGINE_TILED, THIN_ENGINE_STEP = 0, 1, 2
+THIN_ENGINE_AUTO, THIN_ENGINE_TILED, THIN_ENGINE_STEP, THIN_ENGINE_PERSIST, THIN_ENGINE_COOP = (
+    0, 1, 2, 3, 4)
 THIN_FLAG_PROFILE = 1
 
 EXPORTED = [

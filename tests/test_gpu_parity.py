@@ -44,7 +44,10 @@ def assert_same(F, lam, adj, got, st, ref=None):
     assert st.converged
 
 
-@pytest.mark.parametrize("engine", [thin.THIN_ENGINE_TILED, thin.THIN_ENGINE_STEP])
+ENGINES = [thin.THIN_ENGINE_COOP, thin.THIN_ENGINE_TILED, thin.THIN_ENGINE_STEP]
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 def test_blobs_128_lambda0(engine):
     job = synth.blobs_128()
     F = job.image()
@@ -53,20 +56,22 @@ def test_blobs_128_lambda0(engine):
     assert_same(F, job.lam, job.adj, got, st)
 
 
+@pytest.mark.parametrize("engine", ENGINES[:2])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "t%dk%d" % (s[0], s[2]))
-def test_blobs_128_every_tile_shape(shape):
+def test_blobs_128_every_tile_shape(shape, engine):
     job = synth.blobs_128()
     F = job.image()
-    say("case blobs_128 shape", shape)
-    got, st = gpu_thin(F, job.lam, job.adj, tile=shape[0], steps_per_round=shape[2])
+    say("case blobs_128 shape", shape, "engine", engine)
+    got, st = gpu_thin(F, job.lam, job.adj, tile=shape[0], steps_per_round=shape[2], engine=engine)
     assert_same(F, job.lam, job.adj, got, st)
 
 
-def test_ridges_512_lambda20():
+@pytest.mark.parametrize("engine", ENGINES[:2])
+def test_ridges_512_lambda20(engine):
     job = synth.ridges_512()
     F = job.image()
-    say("case ridges_512")
-    got, st = gpu_thin(F, job.lam, job.adj)
+    say("case ridges_512 engine", engine)
+    got, st = gpu_thin(F, job.lam, job.adj, engine=engine)
     assert_same(F, job.lam, job.adj, got, st)
 
 
@@ -101,10 +106,11 @@ def test_schedule_invariance_u16_4_8():
     """Tile shape, halo width and engine change the schedule, never the bytes."""
     F = synth.gen_blobs(150, 201, 77, np.uint16, nblobs=10, sigma=(3.0, 20.0))
     ref = oracle.sweep_dirty(F, 500, 1)
-    for shape in SHAPES:
-        say("case invariance shape", shape)
-        got, st = gpu_thin(F, 500, 1, tile=shape[0], steps_per_round=shape[2])
-        assert_same(F, 500, 1, got, st, ref)
+    for engine in ENGINES[:2]:
+        for shape in SHAPES:
+            say("case invariance shape", shape, "engine", engine)
+            got, st = gpu_thin(F, 500, 1, tile=shape[0], steps_per_round=shape[2], engine=engine)
+            assert_same(F, 500, 1, got, st, ref)
     got, st = gpu_thin(F, 500, 1, engine=thin.THIN_ENGINE_STEP)
     assert_same(F, 500, 1, got, st, ref)
 
@@ -133,14 +139,15 @@ def test_batch_equals_oracle_per_image():
         assert_same(F, lam, adj, t.cpu().numpy(), st)
 
 
-def test_pass_cap_then_resume():
+@pytest.mark.parametrize("engine", ENGINES)
+def test_pass_cap_then_resume(engine):
     F = synth.gen_blobs(90, 70, 123)
     full = oracle.sweep(F, 0)
     part = oracle.sweep(F, 0, max_passes=3)
     assert part.limited
-    say("case pass cap")
+    say("case pass cap engine", engine)
     t = torch.from_numpy(F.copy()).cuda()
-    with thin.Context(max_passes=3) as ctx:
+    with thin.Context(max_passes=3, engine=engine) as ctx:
         st = ctx.run(t, 0, 0, allow_limit=True)
         assert not st.converged and st.passes == 3 and st.lowerings == part.lowerings
         assert np.array_equal(t.cpu().numpy(), part.image)
@@ -174,3 +181,21 @@ def test_degenerate_sizes(shape):
     ref = oracle.sweep(F, 0)
     assert np.array_equal(t.cpu().numpy(), ref.image)
     assert st.passes == ref.passes and st.lowerings == ref.lowerings
+
+
+@pytest.mark.skip(reason="persistent engine disabled: one launch ran past its time guards "
+                         "without finishing and the cause is not established")
+def test_persistent_engine_blobs_128():
+    job = synth.blobs_128()
+    F = job.image()
+    got, st = gpu_thin(F, job.lam, job.adj, engine=thin.THIN_ENGINE_PERSIST)
+    assert_same(F, job.lam, job.adj, got, st)
+
+
+def test_persistent_engine_reports_disabled():
+    F = synth.gen_blobs(16, 16, 1)
+    t = torch.from_numpy(F).cuda()
+    with thin.Context(engine=thin.THIN_ENGINE_PERSIST) as ctx:
+        with pytest.raises(thin.ThinError):
+            ctx.run(t, 0, 0)
+    assert np.array_equal(t.cpu().numpy(), F)
