@@ -91,7 +91,24 @@ def cpu_baseline(images, budget_s: float):
     return px / dt / 1e6, n, dt
 
 
-def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, profile=True):
+def _kernel_pass(ctx_kw, inputs, job_args, run):
+    """Runs `run` over `inputs` with per-launch HIP events on the library's
+    stream; returns (launches, kernel_ms)."""
+    import torch
+    from paper_1603_09180_amd import thin
+
+    ctx = thin.Context(device=0, profile=True, **ctx_kw)
+    torch.cuda.synchronize()
+    ctx.profile(reset=True)
+    for t in inputs:
+        run(ctx, t, *job_args)
+    torch.cuda.synchronize()
+    prof = ctx.profile(reset=True)
+    ctx.close()
+    return int(prof.launches), float(prof.kernel_ms)
+
+
+def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0):
     import numpy as np
     import torch
 
@@ -105,13 +122,13 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, profile=Tru
     src = torch.from_numpy(F).cuda()
     inputs = [src.clone() for _ in range(warmup + steps)]
     torch.cuda.synchronize()
-    ctx = thin.Context(device=0, profile=profile, tile=tile, steps_per_round=k, engine=engine)
+    ctx_kw = dict(tile=tile, steps_per_round=k, engine=engine)
+    ctx = thin.Context(device=0, **ctx_kw)
     for i in range(warmup):
         ctx.run(inputs[i], job.lam, job.adj)
     torch.cuda.synchronize()
-    got = inputs[0].cpu().numpy()
-    bit_exact = bool(np.array_equal(got, ref.image))
-    ctx.profile(reset=True)
+    bit_exact = bool(np.array_equal(inputs[0].cpu().numpy(), ref.image))
+    # Timed region: exactly `steps` runs, no per-launch events.
     lat = []
     stats = None
     torch.cuda.synchronize()
@@ -122,17 +139,21 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, profile=Tru
         lat.append((time.perf_counter() - s0) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = ctx.profile(reset=True)
     ctx.close()
     last = inputs[warmup + steps - 1].cpu().numpy()
     bit_exact = bit_exact and bool(np.array_equal(last, ref.image))
     bit_exact = bit_exact and (stats.passes, stats.lowerings) == (ref.passes, ref.lowerings)
 
+    # Kernel durations: the same runs again on fresh copies, each round
+    # kernel bracketed by HIP events on the library's stream.
+    again = [src.clone() for _ in range(steps)]
+    launches, kernel_ms = _kernel_pass(ctx_kw, again, (job.lam, job.adj),
+                                       lambda c, t, lam, adj: c.run(t, lam, adj))
+    launches = max(launches, 1)
     elapsed = t1 - t0
     mpx = h * w * steps / elapsed / 1e6
     alg_bytes = 2 * b * h * w * ref.passes * steps
-    launches = max(int(prof.launches), 1)
-    kernel_s = prof.kernel_ms / 1e3
+    kernel_s = kernel_ms / 1e3
     achieved = alg_bytes / kernel_s / 1e9 if kernel_s > 0 else None
     traffic = _traffic_for("k_round", name)
     out = {
@@ -151,7 +172,8 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, profile=Tru
         "config": {"workload": name, "h": h, "w": w, "lambda": job.lam,
                    "adjacency": "8,4" if job.adj == 0 else "4,8", "images_per_step": 1,
                    "path": "plain (thin_run)",
-                   "engine": {0: "auto", 1: "tiled", 2: "step", 3: "persistent", 4: "cooperative"}[engine]},
+                   "engine": {0: "auto", 1: "tiled", 2: "step", 3: "persistent",
+                              4: "cooperative"}[engine]},
         "images_per_s": round(steps / elapsed, 2),
         "latency_ms_p50": round(_percentile(lat, 0.5), 4),
         "latency_ms_p99": round(_percentile(lat, 0.99), 4),
@@ -167,9 +189,10 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, profile=Tru
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
             "traffic": traffic,
             "launches_per_step": round(launches / steps, 2),
-            "avg_launch_us": round(prof.kernel_ms * 1e3 / launches, 3),
+            "avg_launch_us": round(kernel_ms * 1e3 / launches, 3),
             "alg_bytes_per_launch": round(alg_bytes / launches, 1),
             "kernel_time_frac_of_step": round(kernel_s / elapsed, 4),
+            "timing": "kernel durations from HIP events in a second pass over the same runs",
         },
     }
     if cpu_s > 0:
@@ -179,6 +202,23 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, profile=Tru
                                "sample": f"ORACLE-SWEEP-DIRTY, single-thread C, {n} run(s) of the "
                                          f"same {h}x{w} image in {dt:.1f} s"}
     return out
+
+
+def copy_calibration(nbytes=1 << 28, reps=20):
+    """A plain device copy of known size, for scaling rocprofv3 HBM counters."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": "copy_calibration", "bytes_read_per_copy": nbytes,
+            "bytes_written_per_copy": nbytes, "copies": reps,
+            "GBps": round(2 * nbytes * reps / dt / 1e9, 1)}
 
 
 def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512):
@@ -194,19 +234,18 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512):
     srcs = [torch.from_numpy(F).cuda() for F in Fs]
     lams = [j.lam for j in jobs]
     adjs = [j.adj for j in jobs]
-    ctx = thin.Context(device=0, profile=True, tile=tile, steps_per_round=k, engine=engine)
+    ctx_kw = dict(tile=tile, steps_per_round=k, engine=engine)
+    ctx = thin.Context(device=0, **ctx_kw)
     sets = [[s.clone() for s in srcs] for _ in range(warmup + steps)]
     torch.cuda.synchronize()
     for i in range(warmup):
         ctx.run_batch(sets[i], lams, adjs)
     torch.cuda.synchronize()
-    ctx.profile(reset=True)
     t0 = time.perf_counter()
     for i in range(steps):
         stats = ctx.run_batch(sets[warmup + i], lams, adjs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = ctx.profile(reset=True)
     # the same images, one plain call each
     plain = [s.clone() for s in srcs]
     torch.cuda.synchronize()
@@ -216,9 +255,13 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512):
     torch.cuda.synchronize()
     p1 = time.perf_counter()
     ctx.close()
-    # bit-exactness on a sample: the 12 smallest images and every 64th
+    launches, kernel_ms = _kernel_pass(ctx_kw, [[s.clone() for s in srcs]], (lams, adjs),
+                                       lambda c, ts, l, a: c.run_batch(ts, l, a))
+    # bit-exactness on a sample the oracle finishes quickly: the 12 smallest
+    # images and every 16th image of at most 0.3 Mpixel
     order = sorted(range(n_images), key=lambda i: Fs[i].size)
-    sample = sorted(set(order[:12]) | set(range(0, n_images, 64)))
+    small = [i for i in range(n_images) if Fs[i].size <= 300_000]
+    sample = sorted(set(order[:12]) | set(small[::16]))
     exact = True
     for i in sample:
         ref = oracle.sweep_dirty(Fs[i], lams[i], adjs[i])
@@ -227,9 +270,9 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512):
         exact &= (stats[i].passes, stats[i].lowerings) == (ref.passes, ref.lowerings)
         exact &= bool(np.array_equal(plain[i].cpu().numpy(), ref.image))
     elapsed = t1 - t0
-    alg = sum(2 * F.size * st.passes for F, st in zip(Fs, stats)) * steps
-    kernel_s = prof.kernel_ms / 1e3
-    achieved = alg / kernel_s / 1e9 if kernel_s > 0 else None
+    alg_one = sum(2 * F.size * st.passes for F, st in zip(Fs, stats))
+    kernel_s = kernel_ms / 1e3
+    achieved = alg_one / kernel_s / 1e9 if kernel_s > 0 else None
     out = {
         "metric": METRIC,
         "value": round(total_px * steps / elapsed / 1e6, 3),
@@ -244,6 +287,7 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512):
         "images_per_s": round(n_images * steps / elapsed, 2),
         "plain_images_per_s": round(n_images / (p1 - p0), 2),
         "plain_mpixel_per_s": round(total_px / (p1 - p0) / 1e6, 3),
+        "streaming_equiv_frac_of_hbm": round(alg_one * steps / elapsed / 1e9 / HBM_PEAK_GBS, 4),
         "bit_exact_sample": exact,
         "roofline": {
             "bound": "hbm", "kernel": "k_round",
@@ -251,8 +295,9 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512):
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
             "traffic": _traffic_for("k_round", "batch_512"),
-            "launches_per_step": round(prof.launches / steps, 2),
-            "avg_launch_us": round(prof.kernel_ms * 1e3 / max(prof.launches, 1), 3),
+            "launches_per_step": launches,
+            "avg_launch_us": round(kernel_ms * 1e3 / max(launches, 1), 3),
+            "timing": "kernel durations from HIP events in a second pass over the same batch",
         },
     }
     if cpu_s > 0:
@@ -271,15 +316,14 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ridges_512",
-                    choices=["ridges_512", "blobs_128", "blobs_8192_u16", "batch_512"])
+                    choices=["ridges_512", "blobs_128", "blobs_8192_u16", "batch_512",
+                             "copy_calibration"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU budget of the oracle baseline (0 disables it)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--k", type=int, default=0)
     ap.add_argument("--engine", type=int, default=0,
                     help="0 auto, 1 tiled, 2 step, 3 persistent (disabled), 4 cooperative")
-    ap.add_argument("--no-profile", action="store_true",
-                    help="time without per-launch HIP events (roofline fields become null)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -292,6 +336,9 @@ def main():
     _ensure_built()
     from paper_1603_09180_amd import synth
 
+    if args.workload == "copy_calibration":
+        print(json.dumps(copy_calibration()), flush=True)
+        return
     if args.workload == "batch_512":
         out = bench_batch(args.steps, args.warmup, args.cpu_seconds, args.tile, args.k,
                           args.engine)
@@ -299,7 +346,7 @@ def main():
         job = {"ridges_512": synth.ridges_512, "blobs_128": synth.blobs_128,
                "blobs_8192_u16": synth.blobs_8192_u16}[args.workload]()
         out = bench_single(job, args.workload, args.steps, args.warmup, args.cpu_seconds,
-                           args.tile, args.k, args.engine, not args.no_profile)
+                           args.tile, args.k, args.engine)
     print(json.dumps(out), flush=True)
 
 
