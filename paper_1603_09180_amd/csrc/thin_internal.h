@@ -54,15 +54,23 @@ void build_topology_table(int adjacency, TopoEntry out[256]);
 
 // Tiled engine geometry chosen at run time among the compiled variants.
 struct TileShape {
-    int th, tw, k;
+    int th, tw, k;   // tile height, width, halo = parity steps per residency
+    int nt;          // threads per tile
+    bool seed;       // residencies seed their dirty flags from the previous round
 };
+
+// The compiled shape with this tile and halo (nt = 0 when there is none).
+TileShape complete_shape(int th, int tw, int k);
 
 // Kernel launchers (thin_kernels.hip).  All enqueue on `stream`.
 hipError_t launch_init_state(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t* tile_last,
-                             int ntiles);
+                             int ntiles, int32_t* hist_round);
 hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                         const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
-                        const TopoEntry* lut, int grid_blocks);
+                        const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
+                        int32_t* hist_round);
+// Words of one tile's change bitmap (two copies of ntiles bitmaps are needed).
+int history_words(TileShape s);
 hipError_t launch_step(hipStream_t stream, const ImgDev* img_host, const ImgDev* img_dev,
                        ImgCnt* cnt, int step, const TopoEntry* lut);
 hipError_t launch_persist(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
@@ -73,7 +81,7 @@ hipError_t launch_persist(hipStream_t stream, TileShape shape, const ImgDev* img
 hipError_t launch_coop(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                        const int32_t* tile_img, int32_t* tile_last, int ntiles,
                        const TopoEntry* lut, int32_t* active, int32_t* rounds_out,
-                       int max_rounds, int num_cus);
+                       int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round);
 hipError_t launch_init_persist(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t* tile_last,
                                int32_t* progress, int ntiles, int32_t* ring, int nring,
                                Sched* sched);

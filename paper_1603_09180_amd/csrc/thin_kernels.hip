@@ -82,16 +82,18 @@ __device__ __forceinline__ void store_px(void* base, int dtype, int64_t idx, uin
 
 // ------------------------------------------------------------------ k_init
 
-__global__ void k_init_state(ImgCnt* cnt, int nimg, int32_t* tile_last, int ntiles)
+__global__ void k_init_state(ImgCnt* cnt, int nimg, int32_t* tile_last, int ntiles,
+                             int32_t* hist_round)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (hist_round && i < 2 * ntiles) hist_round[i] = -1;
     if (i < nimg) {
         cnt[i].lowerings = 0ull;
         cnt[i].tile_rounds = 0ull;
         cnt[i].last_step = -1;
         cnt[i].final_round = -1;
     }
-    if (i < ntiles) tile_last[i] = -1;
+    if (tile_last && i < 2 * ntiles) tile_last[i] = -1;
 }
 
 // ------------------------------------------------------------------ k_step
@@ -162,17 +164,56 @@ __device__ __forceinline__ void* round_dst(const ImgDev* d, int r)
     return d->buf[(r + 1) & 1];
 }
 
+// History handed from one round to the next: for every tile processed in a
+// round, a bitmap (TH rows of TW/32 words) of the interior pixels that were
+// lowered during the last 4 steps of its residency, and the round it was
+// written in.  Two copies alternate by round parity, so a tile of round r
+// reads its neighbours' round r-1 bitmaps while they may be writing their
+// round r ones.
+struct Seed {
+    const uint32_t* prev_bits;   // copy written in round r - 1 (unused when r == 0)
+    const int32_t* prev_round;
+    uint32_t* cur_bits;          // copy this round writes
+    int32_t* cur_round;
+    int r;                       // image-local round of the residency
+    int tile0, tiles_x, tiles_y; // tile grid of the image
+    int ty, tx, g;               // this tile
+};
+
+// Word `a` (global columns 32a..32a+31) of row gi of the previous round's
+// change bitmaps; 0 outside the tile grid or where a tile has no bitmap for
+// round r - 1 (it was skipped then, so nothing in it changed).
+template <int TH, int TW>
+__device__ __forceinline__ uint32_t history_word_t(const Seed* sd, int gi, int a)
+{
+    constexpr int WPR = TW / 32;
+    if (a < 0) return 0u;
+    const int tcol = a / WPR, trow = gi / TH;
+    if (tcol >= sd->tiles_x || trow >= sd->tiles_y) return 0u;
+    const int n = sd->tile0 + trow * sd->tiles_x + tcol;
+    if (sd->prev_round[n] != sd->r - 1) return 0u;
+    return sd->prev_bits[((int64_t)n * TH + (gi - trow * TH)) * WPR + (a - tcol * WPR)];
+}
+
 // Geometry of a tile residency: a TH x TW interior plus a K-pixel halo,
 // staged in LDS as u16, processed by NT threads.
-template <int TH, int TW, int K, int NT>
+template <int TH, int TW, int K, int NT, bool SEED>
 struct Tile {
     static constexpr int RH = TH + 2 * K;
     static constexpr int RW = TW + 2 * K;
     static constexpr int RWP = RW;  // LDS row pitch in elements
     // lanes across a candidate row: next power of two >= RW/2, at most 64
-    static constexpr int LW = (RW / 2 <= 8) ? 8 : (RW / 2 <= 16) ? 16 : (RW / 2 <= 32) ? 32 : 64;
+    static constexpr int LAT_H = RH / 2, LAT_W = RW / 2;  // candidate lattice of one class
+    static constexpr int PPT = (LAT_H * LAT_W + NT - 1) / NT;  // lattice cells per thread
+    static constexpr int WPR = TW >= 32 ? TW / 32 : 1;  // bitmap words per interior row
+    static constexpr int RWW = (RW + 31) / 32;           // change-map words per region row
+    // LDS words of the history arrays (one when the residency keeps no history)
+    static constexpr int BITS_WORDS = SEED ? TH * WPR : 1;
+    static constexpr int CW_WORDS = SEED ? RH * RWW : 1;
     static_assert(K <= TH && K <= TW, "halo must not exceed the tile side");
-    static_assert(NT % LW == 0, "thread count must cover whole candidate rows");
+    static_assert(!SEED || TW % 32 == 0, "history bitmaps need a tile width multiple of 32");
+    static_assert(!SEED || 2 * K <= TH, "history seeding needs the region inside the 3x3 tile block");
+    static_assert(TH % 2 == 0 && TW % 2 == 0 && K % 2 == 0, "tile sides and halo must be even");
 
     // Interior copy src -> dst (a stable tile keeping the ping-pong pair equal).
     static __device__ void copy_interior(const View d, int gy0, int gx0, const void* src,
@@ -203,16 +244,29 @@ struct Tile {
     // clean candidates changes nothing.  Within a step no candidate reads or
     // writes another candidate's flag: the 8 neighbours of a candidate belong
     // to other parity classes.
+    //
+    // With a Seed (sd != nullptr, round > 0) the flags start from history
+    // instead: a candidate examined at step t0 + tau (tau < 4) was last
+    // examined at step t0 + tau - 4, in the previous round, by the tile that
+    // owned it (or earlier, by a tile that was then skipped because its
+    // neighbourhood was quiet).  Only pixels lowered during the last 4 steps
+    // of that round can have changed its 3x3 since, so the 3x3 of each such
+    // pixel is marked.  The region lies inside the 3x3 tile block (K <= tile
+    // side / 2), so the neighbours' bitmaps hold every pixel that matters.
     static __device__ int run(const View d, int gy0, int gx0, int t0, int nsteps,
                               const void* src, void* dst, uint16_t* s_img, uint8_t* s_dirty,
+                              uint32_t* s_bits, uint32_t* s_cw, const Seed* sd,
                               const TopoEntry* lut, int* s_count, int* s_last, int tid,
                               int& last_tau)
     {
         const int ry0 = gy0 - K, rx0 = gx0 - K;
+        const bool seeded = SEED && sd != nullptr && sd->r > 0;
         if (tid == 0) {
             *s_count = 0;
             *s_last = -1;
         }
+        if constexpr (SEED)
+            for (int i = tid; i < TH * WPR; i += NT) s_bits[i] = 0u;
         // All global loads of the region are issued before the first one is
         // waited for.  Zeros outside the image are never read by a candidate:
         // every candidate is an interior pixel whose 3x3 lies inside the image.
@@ -233,28 +287,75 @@ struct Tile {
             const int y = idx / RW, x = idx - y * RW;
             if (idx < RH * RW) {
                 s_img[y * RWP + x] = (uint16_t)vals[k];
-                s_dirty[y * RWP + x] = 1;
+                s_dirty[y * RWP + x] = seeded ? 0 : 1;
             }
         }
         __syncthreads();
+        if constexpr (SEED) if (seeded) {
+            // Change map of the region in 32-pixel words (row y, word j covers
+            // region columns 32j..32j+31), gathered from the neighbours'
+            // tile-aligned bitmaps with a funnel shift, then dilated by the 3x3
+            // and expanded into the byte flags.
+            for (int it = tid; it < RH * RWW; it += NT) {
+                const int y = it / RWW, j = it - y * RWW;
+                const int gi = ry0 + y;
+                uint32_t word = 0u;
+                if (gi >= 0 && gi < d.h) {
+                    const int c0 = rx0 + 32 * j;                  // first global column
+                    const int a = (c0 >= 0) ? (c0 >> 5) : -((31 - c0) >> 5);
+                    const int sh = c0 - 32 * a;                   // 0..31
+                    const uint32_t lo = history_word_t<TH, TW>(sd, gi, a);
+                    const uint32_t hi = history_word_t<TH, TW>(sd, gi, a + 1);
+                    word = sh ? ((lo >> sh) | (hi << (32 - sh))) : lo;
+                }
+                s_cw[it] = word;
+            }
+            __syncthreads();
+            for (int it = tid; it < RH * RWW; it += NT) {
+                const int y = it / RWW, j = it - y * RWW;
+                uint32_t m = 0u;
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const int yy = y + dy;
+                    if (yy < 0 || yy >= RH) continue;
+                    const uint32_t c = s_cw[yy * RWW + j];
+                    const uint32_t l = j > 0 ? s_cw[yy * RWW + j - 1] : 0u;
+                    const uint32_t r = j + 1 < RWW ? s_cw[yy * RWW + j + 1] : 0u;
+                    m |= c | (c << 1) | (c >> 1) | (l >> 31) | (r << 31);
+                }
+                uint8_t* row = s_dirty + y * RWP + 32 * j;
+                const int n = min(32, RW - 32 * j);
+                for (int b = 0; b < n; ++b) row[b] = (uint8_t)((m >> b) & 1u);
+            }
+            __syncthreads();
+        }
 
         const uint32_t lambda = d.lambda;
         int my_count = 0;
+        // Each thread owns fixed positions of the candidate lattice (one in
+        // four pixels, rows and columns of the step's parity): the region's
+        // origin is even (tile side and halo are even), so the candidate of
+        // lattice cell (a, b) in class (si, sj) is region pixel
+        // (2a + si, 2b + sj).  The exact region and the image interior only
+        // mask cells out step by step.
+        int cell_r[PPT], cell_c[PPT];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int idx = tid + k * NT;
+            cell_r[k] = idx < LAT_H * LAT_W ? (idx / LAT_W) * 2 : RH;  // RH: never in range
+            cell_c[k] = idx < LAT_H * LAT_W ? (idx % LAT_W) * 2 : 0;
+        }
         for (int tau = 0; tau < nsteps; ++tau) {
             const int s = (t0 + tau) & 3, si = s >> 1, sj = s & 1;
             // Exact region after tau steps, clipped to the image interior.
             const int r_lo = max(tau + 1, 1 - ry0), r_hi = min(RH - 2 - tau, d.h - 2 - ry0);
             const int c_lo = max(tau + 1, 1 - rx0), c_hi = min(RW - 2 - tau, d.w - 2 - rx0);
-            const int r_first = r_lo + ((si - ry0 - r_lo) & 1);
-            const int c_first = c_lo + ((sj - rx0 - c_lo) & 1);
-            const int na = r_hi >= r_first ? (r_hi - r_first) / 2 + 1 : 0;
-            const int nb = c_hi >= c_first ? (c_hi - c_first) / 2 + 1 : 0;
             bool inner = false;
-            for (int a = tid / LW; a < na; a += NT / LW) {
-                const int lr = r_first + 2 * a;
-                for (int b = tid % LW; b < nb; b += LW) {
-                    const int lc = c_first + 2 * b;
-                    const int o = lr * RWP + lc;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const int lr = cell_r[k] + si, lc = cell_c[k] + sj;
+                if (lr < r_lo || lr > r_hi || lc < c_lo || lc > c_hi) continue;
+                const int o = lr * RWP + lc;
+                {
                     if (!s_dirty[o]) continue;
                     s_dirty[o] = 0;
                     uint16_t* p = s_img + o;
@@ -271,6 +372,12 @@ struct Tile {
                         if (lr >= K && lr < K + TH && lc >= K && lc < K + TW) {
                             ++my_count;
                             inner = true;
+                            if constexpr (SEED) {
+                                if (tau >= nsteps - 4) {
+                                    const int y = lr - K, x = lc - K;
+                                    atomicOr(&s_bits[y * WPR + (x >> 5)], 1u << (x & 31));
+                                }
+                            }
                         }
                     }
                 }
@@ -289,6 +396,13 @@ struct Tile {
         }
         if (my_count) atomicAdd(s_count, my_count);
         __syncthreads();
+        if constexpr (SEED) {
+            if (sd != nullptr) {
+                for (int i = tid; i < TH * WPR; i += NT)
+                    sd->cur_bits[(int64_t)sd->g * TH * WPR + i] = s_bits[i];
+                if (tid == 0) sd->cur_round[sd->g] = sd->r;
+            }
+        }
         last_tau = *s_last;
         return *s_count;
     }
@@ -318,13 +432,14 @@ __device__ __forceinline__ int32_t neighbourhood_last(const ImgDev* d, const int
 // One tile of one round (launch-per-round and cooperative engines).
 // Returns 1 when the tile was processed (active), 0 when skipped.  All NT
 // threads must call it together.
-template <int TH, int TW, int K, int NT>
+template <int TH, int TW, int K, int NT, bool SEED>
 __device__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
-                          const int32_t* __restrict__ tile_img, int32_t* tile_last, int g,
-                          int round, uint16_t* s_img, uint8_t* s_dirty, const TopoEntry* s_lut,
-                          int* s_count, int* s_last)
+                          const int32_t* __restrict__ tile_img, int32_t* tile_state, int g,
+                          int round, int ntiles, uint32_t* hist_bits, int32_t* hist_round,
+                          uint16_t* s_img, uint8_t* s_dirty, uint32_t* s_bits, uint32_t* s_cw,
+                          const TopoEntry* s_lut, int* s_count, int* s_last)
 {
-    using T = Tile<TH, TW, K, NT>;
+    using T = Tile<TH, TW, K, NT, SEED>;
     const int tid = threadIdx.x;
     const int ii = tile_img[g];
     const ImgDev* d = imgs + ii;
@@ -336,14 +451,24 @@ __device__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
     const int lt = g - d->tile0;
     const int ty = lt / d->tiles_x, tx = lt - ty * d->tiles_x;
 
-    // Neighbouring tiles of this round may update their tile_last while it
-    // is read here (values only grow, which can only add work), so one thread
-    // decides and the barrier broadcasts a block-uniform answer.  The barrier
-    // also orders this tile's LDS writes after the previous tile's readers.
+    // tile_state[2g] is the latest round for which a tile of g's 3x3 tile
+    // neighbourhood asked g to be active (it lowered something during the
+    // last 4 steps of the round before); tile_state[2g + 1] is the last round
+    // in which g itself lowered something.  Neighbours of this round may raise
+    // tile_state[2g] to r + 1 while it is read here (only adding work), so one
+    // thread decides and the barrier broadcasts a block-uniform answer; the
+    // barrier also orders this tile's LDS writes after the previous tile's
+    // readers.
     int vote = 0;
-    if (tid == 0) vote = (r == 0 || neighbourhood_last(d, tile_last, ty, tx) >= t0 - 4) ? 1 : 0;
-    const bool active = __syncthreads_or(vote) != 0;
-    const int32_t own_last = tile_last[g];  // written only by this tile's residencies
+    if (tid == 0) {
+        const int act = __hip_atomic_load(&tile_state[2 * g], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        const int chg = __hip_atomic_load(&tile_state[2 * g + 1], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        vote = (r == 0 || act >= r) ? 1 : (chg == r - 1 ? 2 : 0);
+    }
+    const int decision = __syncthreads_or(vote == 1) ? 1 : (__syncthreads_or(vote == 2) ? 2 : 0);
+    const bool active = decision == 1;
     const void* src = round_src(d, r);
     void* dst = round_dst(d, r);
     const int gy0 = ty * TH, gx0 = tx * TW;
@@ -352,39 +477,72 @@ __device__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
     if (!active) {
         // Stable for this round.  The output buffer already equals the input
         // unless the tile changed during the previous round.
-        if (own_last >= t0 - K) T::copy_interior(v, gy0, gx0, src, dst, tid);
+        if (decision == 2) T::copy_interior(v, gy0, gx0, src, dst, tid);
         return 0;
     }
+    Seed sd{};
+    const int64_t words = SEED ? (int64_t)ntiles * TH * T::WPR : 0;
+    sd.prev_bits = hist_bits + ((r + 1) & 1) * words;
+    sd.prev_round = hist_round + ((r + 1) & 1) * ntiles;
+    sd.cur_bits = hist_bits + (r & 1) * words;
+    sd.cur_round = hist_round + (r & 1) * ntiles;
+    sd.r = r;
+    sd.tile0 = d->tile0;
+    sd.tiles_x = d->tiles_x;
+    sd.tiles_y = d->tiles_y;
+    sd.ty = ty;
+    sd.tx = tx;
+    sd.g = g;
     int last_tau;
-    const int count = T::run(v, gy0, gx0, t0, nsteps, src, dst, s_img, s_dirty,
-                             s_lut + d->adj * 256, s_count, s_last, tid, last_tau);
+    const int count = T::run(v, gy0, gx0, t0, nsteps, src, dst, s_img, s_dirty, s_bits, s_cw,
+                             SEED ? &sd : nullptr, s_lut + d->adj * 256, s_count, s_last, tid,
+                             last_tau);
     if (tid == 0) {
         atomicAdd(&cnt[ii].tile_rounds, 1ull);
         if (last_tau >= 0) {
-            __hip_atomic_store(&tile_last[g], t0 + last_tau, __ATOMIC_RELAXED,
+            __hip_atomic_store(&tile_state[2 * g + 1], r, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
             atomicAdd(&cnt[ii].lowerings, (unsigned long long)count);
             atomicMax(&cnt[ii].last_step, t0 + last_tau);
+        }
+        // Lowered during the last 4 steps: the 3x3 tile block must run the next
+        // round (a tile whose whole block was quiet for 4 steps cannot change
+        // within the next K <= tile-side steps).
+        if (last_tau >= nsteps - 4) {
+            for (int dy = -1; dy <= 1; ++dy) {
+                const int y = ty + dy;
+                if (y < 0 || y >= d->tiles_y) continue;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int x = tx + dx;
+                    if (x < 0 || x >= d->tiles_x) continue;
+                    __hip_atomic_fetch_max(&tile_state[2 * (d->tile0 + y * d->tiles_x + x)],
+                                           r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
         }
     }
     return 1;
 }
 
-template <int TH, int TW, int K, int NT>
+template <int TH, int TW, int K, int NT, bool SEED>
 __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                                               const int32_t* __restrict__ tile_img,
                                               int32_t* tile_last, int ntiles, int round,
-                                              const TopoEntry* __restrict__ lut_g)
+                                              const TopoEntry* __restrict__ lut_g,
+                                              uint32_t* hist_bits, int32_t* hist_round)
 {
-    using T = Tile<TH, TW, K, NT>;
+    using T = Tile<TH, TW, K, NT, SEED>;
     __shared__ uint16_t s_img[T::RH * T::RWP];
     __shared__ uint8_t s_dirty[T::RH * T::RWP];
+    __shared__ uint32_t s_bits[T::BITS_WORDS];
+    __shared__ uint32_t s_cw[T::CW_WORDS];
     __shared__ TopoEntry s_lut[512];
     __shared__ int s_count, s_last;
     for (int i = threadIdx.x; i < 512; i += NT) s_lut[i] = lut_g[i];
     for (int g = blockIdx.x; g < ntiles; g += gridDim.x)
-        round_tile<TH, TW, K, NT>(imgs, cnt, tile_img, tile_last, g, round, s_img, s_dirty, s_lut,
-                                  &s_count, &s_last);
+        round_tile<TH, TW, K, NT, SEED>(imgs, cnt, tile_img, tile_last, g, round, ntiles, hist_bits,
+                                  hist_round, s_img, s_dirty, s_bits, s_cw, s_lut, &s_count,
+                                  &s_last);
 }
 
 // ------------------------------------------------------------------ k_coop
@@ -398,16 +556,19 @@ __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, I
 // grid barrier of round r and is cleared during round r + 2, after the next
 // barrier has proved those reads complete.
 
-template <int TH, int TW, int K, int NT>
+template <int TH, int TW, int K, int NT, bool SEED>
 __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                                              const int32_t* __restrict__ tile_img,
                                              int32_t* tile_last, int ntiles,
                                              const TopoEntry* __restrict__ lut_g, int32_t* active,
-                                             int32_t* rounds_out, int max_rounds)
+                                             int32_t* rounds_out, int max_rounds,
+                                             uint32_t* hist_bits, int32_t* hist_round)
 {
-    using T = Tile<TH, TW, K, NT>;
+    using T = Tile<TH, TW, K, NT, SEED>;
     __shared__ uint16_t s_img[T::RH * T::RWP];
     __shared__ uint8_t s_dirty[T::RH * T::RWP];
+    __shared__ uint32_t s_bits[T::BITS_WORDS];
+    __shared__ uint32_t s_cw[T::CW_WORDS];
     __shared__ TopoEntry s_lut[512];
     __shared__ int s_count, s_last;
     const int tid = threadIdx.x;
@@ -420,8 +581,9 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
                                __HIP_MEMORY_SCOPE_AGENT);
         int mine = 0;
         for (int g = blockIdx.x; g < ntiles; g += gridDim.x)
-            mine += round_tile<TH, TW, K, NT>(imgs, cnt, tile_img, tile_last, g, round, s_img,
-                                              s_dirty, s_lut, &s_count, &s_last);
+            mine += round_tile<TH, TW, K, NT, SEED>(imgs, cnt, tile_img, tile_last, g, round, ntiles,
+                                              hist_bits, hist_round, s_img, s_dirty, s_bits, s_cw,
+                                              s_lut, &s_count, &s_last);
         if (tid == 0 && mine) atomicAdd(&active[round % 3], mine);
         // Stores of every wave must be acknowledged before the grid barrier
         // publishes them.
@@ -434,33 +596,35 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
     if (blockIdx.x == 0 && tid == 0) *rounds_out = round + 1;
 }
 
-template <int TH, int TW, int K, int NT>
+template <int TH, int TW, int K, int NT, bool SEED>
 hipError_t launch_coop_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                          const int32_t* tile_img, int32_t* tile_last, int ntiles,
                          const TopoEntry* lut, int32_t* active, int32_t* rounds_out,
-                         int max_rounds, int num_cus)
+                         int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round)
 {
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT>), NT, 0);
+        &per_cu, reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT, SEED>), NT, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     const int grid = max(1, min(ntiles, per_cu * num_cus));
-    void* args[] = {(void*)&imgs,   (void*)&cnt,    (void*)&tile_img,   (void*)&tile_last,
-                    (void*)&ntiles, (void*)&lut,    (void*)&active,     (void*)&rounds_out,
-                    (void*)&max_rounds};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT>),
+    void* args[] = {(void*)&imgs,       (void*)&cnt,       (void*)&tile_img,
+                    (void*)&tile_last,  (void*)&ntiles,    (void*)&lut,
+                    (void*)&active,     (void*)&rounds_out, (void*)&max_rounds,
+                    (void*)&hist_bits,  (void*)&hist_round};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT, SEED>),
                                       dim3(grid), dim3(NT), args, 0, stream);
 }
 
-template <int TH, int TW, int K, int NT>
+template <int TH, int TW, int K, int NT, bool SEED>
 hipError_t launch_round_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                           const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
-                          const TopoEntry* lut, int grid_blocks)
+                          const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
+                          int32_t* hist_round)
 {
     const int grid = max(1, min(ntiles, grid_blocks));
-    hipLaunchKernelGGL((k_round<TH, TW, K, NT>), dim3(grid), dim3(NT), 0, stream, imgs, cnt,
-                       tile_img, tile_last, ntiles, round, lut);
+    hipLaunchKernelGGL((k_round<TH, TW, K, NT, SEED>), dim3(grid), dim3(NT), 0, stream, imgs, cnt,
+                       tile_img, tile_last, ntiles, round, lut, hist_bits, hist_round);
     return hipGetLastError();
 }
 
@@ -494,7 +658,7 @@ __device__ __forceinline__ int ld_sync(int32_t* p)
     return __hip_atomic_fetch_add(p, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int TH, int TW, int K, int NT>
+template <int TH, int TW, int K, int NT, bool SEED>
 __global__ __launch_bounds__(NT) void k_persist(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                                                 const int32_t* __restrict__ tile_img,
                                                 int32_t* tile_last, int32_t* progress,
@@ -503,9 +667,11 @@ __global__ __launch_bounds__(NT) void k_persist(const ImgDev* __restrict__ imgs,
                                                 unsigned long long wait_ticks,
                                                 unsigned long long kernel_ticks)
 {
-    using T = Tile<TH, TW, K, NT>;
+    using T = Tile<TH, TW, K, NT, SEED>;
     __shared__ uint16_t s_img[T::RH * T::RWP];
     __shared__ uint8_t s_dirty[T::RH * T::RWP];
+    __shared__ uint32_t s_bits[T::BITS_WORDS];
+    __shared__ uint32_t s_cw[T::CW_WORDS];
     __shared__ TopoEntry s_lut[512];
     __shared__ int s_count, s_last;
     __shared__ int s_item[4];  // tile, round, active, copy
@@ -599,8 +765,8 @@ __global__ __launch_bounds__(NT) void k_persist(const ImgDev* __restrict__ imgs,
         const View v = view_of(d);
         int last_tau = -1, count = 0;
         if (s_item[2]) {
-            count = T::run(v, gy0, gx0, t0, nsteps, src, dst, s_img, s_dirty, s_lut + d->adj * 256,
-                           &s_count, &s_last, tid, last_tau);
+            count = T::run(v, gy0, gx0, t0, nsteps, src, dst, s_img, s_dirty, s_bits, s_cw,
+                           nullptr, s_lut + d->adj * 256, &s_count, &s_last, tid, last_tau);
         } else if (s_item[3]) {
             T::copy_interior(v, gy0, gx0, src, dst, tid);
         }
@@ -661,14 +827,14 @@ __global__ void k_init_persist(ImgCnt* cnt, int nimg, int32_t* tile_last, int32_
     }
 }
 
-template <int TH, int TW, int K, int NT>
+template <int TH, int TW, int K, int NT, bool SEED>
 hipError_t launch_persist_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                             const int32_t* tile_img, int32_t* tile_last, int32_t* progress,
                             int32_t* ring, Sched* sched, int ntiles, const TopoEntry* lut,
                             int grid_blocks, unsigned long long wait_ticks,
                             unsigned long long kernel_ticks)
 {
-    hipLaunchKernelGGL((k_persist<TH, TW, K, NT>), dim3(max(1, grid_blocks)), dim3(NT), 0, stream,
+    hipLaunchKernelGGL((k_persist<TH, TW, K, NT, SEED>), dim3(max(1, grid_blocks)), dim3(NT), 0, stream,
                        imgs, cnt, tile_img, tile_last, progress, ring, sched, ntiles, lut,
                        wait_ticks, kernel_ticks);
     return hipGetLastError();
@@ -677,12 +843,12 @@ hipError_t launch_persist_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
 }  // namespace
 
 hipError_t launch_init_state(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t* tile_last,
-                             int ntiles)
+                             int ntiles, int32_t* hist_round)
 {
-    const int n = max(nimg, ntiles);
+    const int n = max(nimg, 2 * ntiles);
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_init_state, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                       stream, cnt, nimg, tile_last, ntiles);
+                       stream, cnt, nimg, tile_last, ntiles, hist_round);
     return hipGetLastError();
 }
 
@@ -701,53 +867,66 @@ hipError_t launch_step(hipStream_t stream, const ImgDev* img_host, const ImgDev*
 }
 
 // Compiled tile shapes: (tile height, tile width, halo = steps per residency,
-// threads of the persistent kernel).
-#define THIN_SHAPES(X)   \
-    X(32, 32, 8, 512)    \
-    X(32, 32, 16, 1024)  \
-    X(64, 64, 16, 1024)  \
-    X(64, 64, 32, 1024)
+// threads per tile, history seeding).
+#define THIN_SHAPES(X)           \
+    X(16, 16, 8, 256, false)     \
+    X(32, 32, 8, 256, false)     \
+    X(32, 32, 8, 512, false)     \
+    X(32, 32, 16, 256, false)    \
+    X(32, 32, 16, 1024, false)   \
+    X(32, 32, 16, 1024, true)    \
+    X(64, 64, 16, 1024, false)   \
+    X(64, 64, 16, 1024, true)    \
+    X(64, 64, 32, 1024, false)
 
 bool tile_shape_supported(TileShape s)
 {
-#define X(a, b, c, n) if (s.th == a && s.tw == b && s.k == c) return true;
+#define X(a, b, c, n, e) \
+    if (s.th == a && s.tw == b && s.k == c && s.nt == n && s.seed == e) return true;
     THIN_SHAPES(X)
 #undef X
     return false;
 }
 
-int persist_threads(TileShape s)
+TileShape complete_shape(int th, int tw, int k)
 {
-#define X(a, b, c, n) if (s.th == a && s.tw == b && s.k == c) return n;
+#define X(a, b, c, n, e) \
+    if (th == a && tw == b && k == c) return TileShape{a, b, c, n, e};
     THIN_SHAPES(X)
 #undef X
-    return 0;
+    return TileShape{0, 0, 0, 0, false};
 }
 
-static int lds_bytes(TileShape s) { return (s.th + 2 * s.k) * (s.tw + 2 * s.k) * 3 + 4096 + 64; }
+int persist_threads(TileShape s) { return s.nt; }
+
+static int lds_bytes(TileShape s)
+{
+    const int region = (s.th + 2 * s.k) * (s.tw + 2 * s.k);
+    const int hist = s.seed ? (s.th * (s.tw / 32) + (s.th + 2 * s.k) * ((s.tw + 2 * s.k + 31) / 32)) * 4
+                            : 8;
+    return region * 3 + hist + 4096 + 64;
+}
+
+int history_words(TileShape s) { return s.seed ? s.th * (s.tw / 32) : 1; }
 
 int round_blocks_per_cu(TileShape s)
 {
     const int by_lds = (160 * 1024) / lds_bytes(s);
-    const int by_threads = 2048 / max(64, persist_threads(s));
+    const int by_threads = 2048 / max(64, s.nt);
     return max(1, min(by_lds, by_threads));
 }
 
-int persist_blocks_per_cu(TileShape s)
-{
-    const int by_lds = (160 * 1024) / lds_bytes(s);
-    const int by_threads = 2048 / max(64, persist_threads(s));
-    return max(1, min(by_lds, by_threads));
-}
+int persist_blocks_per_cu(TileShape s) { return round_blocks_per_cu(s); }
 
 hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                         const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
-                        const TopoEntry* lut, int grid_blocks)
+                        const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
+                        int32_t* hist_round)
 {
-#define X(a, b, c, n)                                                                    \
-    if (shape.th == a && shape.tw == b && shape.k == c)                                  \
-        return launch_round_t<a, b, c, n>(stream, imgs, cnt, tile_img, tile_last, ntiles, \
-                                          round, lut, grid_blocks);
+#define X(a, b, c, n, e)                                                                    \
+    if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.seed == e)  \
+        return launch_round_t<a, b, c, n, e>(stream, imgs, cnt, tile_img, tile_last, ntiles, \
+                                             round, lut, grid_blocks, hist_bits, hist_round);
     THIN_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
@@ -759,11 +938,11 @@ hipError_t launch_persist(hipStream_t stream, TileShape shape, const ImgDev* img
                           int grid_blocks, unsigned long long wait_ticks,
                           unsigned long long kernel_ticks)
 {
-#define X(a, b, c, n)                                                                        \
-    if (shape.th == a && shape.tw == b && shape.k == c)                                      \
-        return launch_persist_t<a, b, c, n>(stream, imgs, cnt, tile_img, tile_last, progress, \
-                                            ring, sched, ntiles, lut, grid_blocks, wait_ticks, \
-                                            kernel_ticks);
+#define X(a, b, c, n, e)                                                                     \
+    if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.seed == e)   \
+        return launch_persist_t<a, b, c, n, e>(stream, imgs, cnt, tile_img, tile_last,        \
+                                               progress, ring, sched, ntiles, lut, grid_blocks, \
+                                               wait_ticks, kernel_ticks);
     THIN_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
@@ -772,12 +951,13 @@ hipError_t launch_persist(hipStream_t stream, TileShape shape, const ImgDev* img
 hipError_t launch_coop(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                        const int32_t* tile_img, int32_t* tile_last, int ntiles,
                        const TopoEntry* lut, int32_t* active, int32_t* rounds_out,
-                       int max_rounds, int num_cus)
+                       int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round)
 {
-#define X(a, b, c, n)                                                                        \
-    if (shape.th == a && shape.tw == b && shape.k == c)                                      \
-        return launch_coop_t<a, b, c, n>(stream, imgs, cnt, tile_img, tile_last, ntiles, lut, \
-                                         active, rounds_out, max_rounds, num_cus);
+#define X(a, b, c, n, e)                                                                    \
+    if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.seed == e)  \
+        return launch_coop_t<a, b, c, n, e>(stream, imgs, cnt, tile_img, tile_last, ntiles,  \
+                                            lut, active, rounds_out, max_rounds, num_cus,    \
+                                            hist_bits, hist_round);
     THIN_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;

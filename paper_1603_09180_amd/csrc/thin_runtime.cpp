@@ -16,6 +16,7 @@
 #include <climits>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -53,12 +54,12 @@ struct thin_ctx {
     hipStream_t stream = nullptr;
     uint64_t max_device_bytes = 0;
     uint64_t max_passes = 0;
-    TileShape forced{0, 0, 0};
+    TileShape forced{0, 0, 0, 0, false};
     int num_cus = 256;
 
     TopoEntry* d_lut = nullptr;
     uint64_t allocated = 0;        // bytes of scratch currently held
-    DevBuf twin, imgs, cnt, tile_img, tile_last, progress, ring, sched;
+    DevBuf twin, imgs, cnt, tile_img, tile_last, progress, ring, sched, hist_bits, hist_round;
     unsigned long long wait_ticks = 0;     // dependency-wait limit of the persistent kernel
     unsigned long long kernel_ticks = 0;   // whole-launch limit of the persistent kernel
     ImgCnt* h_snap[2] = {nullptr, nullptr};   // pinned snapshots of the counters
@@ -152,7 +153,8 @@ int ensure_snap(thin_ctx* ctx, size_t n)
 
 // Launches one round, bracketed by timing events when profiling.
 int timed_round(thin_ctx* ctx, size_t& ev_used, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
-                const int32_t* tile_img, int32_t* tile_last, int ntiles, int round, int grid)
+                const int32_t* tile_img, int32_t* tile_last, int ntiles, int round, int grid,
+                uint32_t* hist_bits, int32_t* hist_round)
 {
     if (ctx->profile) {
         while (ctx->prof_ev.size() < ev_used + 2) {
@@ -163,7 +165,7 @@ int timed_round(thin_ctx* ctx, size_t& ev_used, TileShape shape, const ImgDev* i
         HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used], ctx->stream));
     }
     HIP_TRY(ctx, thin::launch_round(ctx->stream, shape, imgs, cnt, tile_img, tile_last, ntiles,
-                                    round, ctx->d_lut, grid));
+                                    round, ctx->d_lut, grid, hist_bits, hist_round));
     if (ctx->profile) {
         HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used + 1], ctx->stream));
         ev_used += 2;
@@ -207,8 +209,8 @@ int steps_cap(const thin_ctx* ctx)
 TileShape choose_shape(const thin_ctx* ctx, int64_t total_pixels)
 {
     if (ctx->forced.th) return ctx->forced;
-    if (total_pixels <= (int64_t)4 << 20) return TileShape{32, 32, 16};
-    return TileShape{64, 64, 16};
+    if (total_pixels <= (int64_t)4 << 20) return TileShape{32, 32, 16, 1024, false};
+    return TileShape{64, 64, 16, 1024, false};
 }
 
 void fill_stats(thin_stats* st, const ImgCnt& c, int steps_done, int max_steps, bool trivial)
@@ -288,18 +290,25 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
     if ((rc = ensure(ctx, ctx->imgs, sizeof(ImgDev) * nimg))) return rc;
     if ((rc = ensure(ctx, ctx->cnt, sizeof(ImgCnt) * nimg))) return rc;
     if ((rc = ensure(ctx, ctx->tile_img, sizeof(int32_t) * ntiles))) return rc;
-    if ((rc = ensure(ctx, ctx->tile_last, sizeof(int32_t) * ntiles))) return rc;
+    if ((rc = ensure(ctx, ctx->tile_last, sizeof(int32_t) * 2 * (size_t)ntiles))) return rc;
+    if ((rc = ensure(ctx, ctx->hist_bits,
+                     sizeof(uint32_t) * 2 * (size_t)ntiles * thin::history_words(shape))))
+        return rc;
+    if ((rc = ensure(ctx, ctx->hist_round, sizeof(int32_t) * 2 * (size_t)ntiles))) return rc;
     if ((rc = ensure_snap(ctx, nimg))) return rc;
 
     ImgDev* d_imgs = static_cast<ImgDev*>(ctx->imgs.ptr);
     ImgCnt* d_cnt = static_cast<ImgCnt*>(ctx->cnt.ptr);
     int32_t* d_tile_img = static_cast<int32_t*>(ctx->tile_img.ptr);
     int32_t* d_tile_last = static_cast<int32_t*>(ctx->tile_last.ptr);
+    uint32_t* d_hist_bits = static_cast<uint32_t*>(ctx->hist_bits.ptr);
+    int32_t* d_hist_round = static_cast<int32_t*>(ctx->hist_round.ptr);
     HIP_TRY(ctx, hipMemcpyAsync(d_imgs, plan.imgs.data(), sizeof(ImgDev) * nimg,
                                 hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(d_tile_img, plan.tile_img.data(), sizeof(int32_t) * ntiles,
                                 hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, nimg, d_tile_last, ntiles));
+    HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, nimg, d_tile_last, ntiles,
+                                         d_hist_round));
 
     const int grid = ctx->num_cus * thin::round_blocks_per_cu(shape);
     const int rounds_cap = (max_steps == INT_MAX) ? INT_MAX : (max_steps + K - 1) / K;
@@ -322,7 +331,7 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
         const int n = std::min(chunk, rounds_cap - launched);
         for (int k = 0; k < n; ++k) {
             if ((rc = timed_round(ctx, ev_used, shape, d_imgs, d_cnt, d_tile_img, d_tile_last,
-                                  ntiles, launched, grid)))
+                                  ntiles, launched, grid, d_hist_bits, d_hist_round)))
                 return rc;
             ++launched;
         }
@@ -427,8 +436,12 @@ int run_coop(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
     if ((rc = ensure(ctx, ctx->imgs, sizeof(ImgDev) * nimg))) return rc;
     if ((rc = ensure(ctx, ctx->cnt, sizeof(ImgCnt) * nimg))) return rc;
     if ((rc = ensure(ctx, ctx->tile_img, sizeof(int32_t) * ntiles))) return rc;
-    if ((rc = ensure(ctx, ctx->tile_last, sizeof(int32_t) * ntiles))) return rc;
+    if ((rc = ensure(ctx, ctx->tile_last, sizeof(int32_t) * 2 * (size_t)ntiles))) return rc;
     if ((rc = ensure(ctx, ctx->sched, 64))) return rc;
+    if ((rc = ensure(ctx, ctx->hist_bits,
+                     sizeof(uint32_t) * 2 * (size_t)ntiles * thin::history_words(shape))))
+        return rc;
+    if ((rc = ensure(ctx, ctx->hist_round, sizeof(int32_t) * 2 * (size_t)ntiles))) return rc;
     if ((rc = ensure_snap(ctx, nimg))) return rc;
 
     ImgDev* d_imgs = static_cast<ImgDev*>(ctx->imgs.ptr);
@@ -441,7 +454,8 @@ int run_coop(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
     HIP_TRY(ctx, hipMemcpyAsync(d_tile_img, plan.tile_img.data(), sizeof(int32_t) * ntiles,
                                 hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemsetAsync(d_small, 0, 4 * sizeof(int32_t), ctx->stream));
-    HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, nimg, d_tile_last, ntiles));
+    HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, nimg, d_tile_last, ntiles,
+                                         static_cast<int32_t*>(ctx->hist_round.ptr)));
     const int rounds_cap = (max_steps == INT_MAX) ? INT_MAX : (max_steps + K - 1) / K;
     size_t ev_used = 0;
     if (ctx->profile) {
@@ -454,7 +468,8 @@ int run_coop(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
     }
     HIP_TRY(ctx, thin::launch_coop(ctx->stream, shape, d_imgs, d_cnt, d_tile_img, d_tile_last,
                                    ntiles, ctx->d_lut, d_small, d_small + 3, rounds_cap,
-                                   ctx->num_cus));
+                                   ctx->num_cus, static_cast<uint32_t*>(ctx->hist_bits.ptr),
+                                   static_cast<int32_t*>(ctx->hist_round.ptr)));
     if (ctx->profile) {
         HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[1], ctx->stream));
         ev_used = 2;
@@ -643,7 +658,7 @@ int run_step_engine(thin_ctx* ctx, const thin_image* ims, const std::vector<int>
         ImgDev* d_img = static_cast<ImgDev*>(ctx->imgs.ptr);
         ImgCnt* d_cnt = static_cast<ImgCnt*>(ctx->cnt.ptr);
         HIP_TRY(ctx, hipMemcpyAsync(d_img, &d, sizeof d, hipMemcpyHostToDevice, ctx->stream));
-        HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, 1, nullptr, 0));
+        HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, 1, nullptr, 0, nullptr));
         int step = 0;
         for (;;) {
             for (int s = 0; s < 4 && step < max_steps; ++s, ++step)
@@ -704,8 +719,20 @@ int thin_create(thin_ctx** out, const thin_config* cfg)
     if (cfg) c = *cfg;
     if (c.engine < 0 || c.engine > THIN_ENGINE_COOP) return THIN_EINVAL;
     if ((c.tile != 0) != (c.steps_per_round != 0)) return THIN_EINVAL;
-    if (c.tile && !thin::tile_shape_supported(TileShape{c.tile, c.tile, c.steps_per_round}))
-        return THIN_EINVAL;
+    TileShape forced{0, 0, 0, 0, false};
+    if (c.tile) {
+        forced = thin::complete_shape(c.tile, c.tile, c.steps_per_round);
+        if (!forced.nt) return THIN_EINVAL;
+    }
+    // THIN_TILE_SHAPE="th,tw,k,threads,seed" selects any compiled shape (tuning).
+    if (const char* env = getenv("THIN_TILE_SHAPE")) {
+        TileShape e{0, 0, 0, 0, false};
+        int seed = 0;
+        if (sscanf(env, "%d,%d,%d,%d,%d", &e.th, &e.tw, &e.k, &e.nt, &seed) == 5) {
+            e.seed = seed != 0;
+            if (thin::tile_shape_supported(e)) forced = e;
+        }
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
         (void)hipGetLastError();
@@ -719,7 +746,7 @@ int thin_create(thin_ctx** out, const thin_config* cfg)
     ctx->stream = static_cast<hipStream_t>(c.hip_stream);
     ctx->max_device_bytes = c.max_device_bytes;
     ctx->max_passes = c.max_passes;
-    if (c.tile) ctx->forced = TileShape{c.tile, c.tile, c.steps_per_round};
+    ctx->forced = forced;
     ctx->profile = (c.flags & THIN_FLAG_PROFILE) != 0;
     int rc = THIN_OK;
     do {
@@ -786,8 +813,9 @@ int thin_destroy(thin_ctx* ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&ctx->twin,     &ctx->imgs, &ctx->cnt,   &ctx->tile_img,  &ctx->tile_last,
-                      &ctx->progress, &ctx->ring, &ctx->sched, &ctx->serve_twin};
+    DevBuf* bufs[] = {&ctx->twin,     &ctx->imgs,      &ctx->cnt,        &ctx->tile_img,
+                      &ctx->tile_last, &ctx->progress, &ctx->ring,       &ctx->sched,
+                      &ctx->hist_bits, &ctx->hist_round, &ctx->serve_twin};
     for (DevBuf* b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->d_lut) (void)hipFree(ctx->d_lut);

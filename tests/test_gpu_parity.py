@@ -102,6 +102,25 @@ def test_fuzz(case):
     assert_same(F, lam, adj, got, st)
 
 
+# Every compiled (tile height, width, halo, threads, history seeding) shape.
+ALL_SHAPES = ["16,16,8,256,0", "32,32,8,256,0", "32,32,8,512,0", "32,32,16,256,0",
+              "32,32,16,1024,0", "32,32,16,1024,1", "64,64,16,1024,0", "64,64,16,1024,1",
+              "64,64,32,1024,0"]
+
+
+@pytest.mark.parametrize("shape", ALL_SHAPES)
+def test_every_compiled_shape(shape, monkeypatch):
+    monkeypatch.setenv("THIN_TILE_SHAPE", shape)
+    F = synth.gen_blobs(150, 201, 77, np.uint16, nblobs=10, sigma=(3.0, 20.0))
+    say("case compiled shape", shape)
+    got, st = gpu_thin(F, 500, 1)
+    assert_same(F, 500, 1, got, st)
+    job = synth.ridges_512()
+    R = job.image()[:300, :260].copy()
+    got, st = gpu_thin(R, 20, 0)
+    assert_same(R, 20, 0, got, st)
+
+
 def test_schedule_invariance_u16_4_8():
     """Tile shape, halo width and engine change the schedule, never the bytes."""
     F = synth.gen_blobs(150, 201, 77, np.uint16, nblobs=10, sigma=(3.0, 20.0))
