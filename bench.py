@@ -10,7 +10,10 @@ library works in place); the timed region brackets exactly --steps runs with
 a device synchronisation on both sides.
 
 Other workloads (--workload): blobs_128, blobs_8192_u16, batch_512 (512
-uneven images in one batched call, compared with 512 plain calls).
+uneven images in one batched call, compared with 512 plain calls), serving
+(Poisson arrivals at 2000 images/s of u8/u16 images with sides 64..4096
+through the continuous-batching calls: throughput with p50/p99 latency from
+arrival to result, and the capacity with every request present at once).
 
 The JSON line carries:
   value      Mpixel/s (pixels of input images thinned to stability per second)
@@ -310,6 +313,114 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512):
     return out
 
 
+def bench_serving(cpu_s, tile, k, seconds=1.0, rate=2000.0, rounds_per_step=2,
+                  budget_gib=16):
+    """Continuous batching under Poisson arrivals (the serving trace), then the
+    same requests all at once (capacity), then a profiled pass for the
+    round-kernel roofline."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1603_09180_amd import serve, synth, thin
+
+    jobs = synth.serving_trace(duration_s=seconds, rate=rate)
+    def make_inputs():
+        return [synth.gen_blobs_device(j.h, j.w, j.seed, j.dtype) for j in jobs]
+
+    def requests(images, at_once=False):
+        return [serve.Request(tag=i, image=im, lam=j.lam, adj=j.adj,
+                              arrival=0.0 if at_once else j.arrival)
+                for i, (j, im) in enumerate(zip(jobs, images))]
+
+    ctx_kw = dict(tile=tile, steps_per_round=k, max_device_bytes=budget_gib << 30)
+    pristine = make_inputs()
+    torch.cuda.synchronize()
+    total_px = sum(j.h * j.w for j in jobs)
+    # warm-up: the first 64 requests, all at once
+    with thin.Context(device=0, **ctx_kw) as ctx:
+        warm = [im.clone() for im in pristine[:64]]
+        serve.replay(ctx, [serve.Request(i, im, j.lam, j.adj, 0.0)
+                           for i, (j, im) in enumerate(zip(jobs[:64], warm))], rounds_per_step)
+        del warm
+        torch.cuda.synchronize()
+        # Poisson arrivals in real time
+        live = [im.clone() for im in pristine]
+        torch.cuda.synchronize()
+        rep = serve.replay(ctx, requests(live), rounds_per_step)
+        torch.cuda.synchronize()
+        # capacity: the same requests all present at t = 0
+        full = [im.clone() for im in pristine]
+        torch.cuda.synchronize()
+        cap = serve.replay(ctx, requests(full, at_once=True), rounds_per_step)
+        torch.cuda.synchronize()
+    # profiled pass (HIP events around every round launch)
+    prof_in = [im.clone() for im in pristine]
+    torch.cuda.synchronize()
+    with thin.Context(device=0, profile=True, **ctx_kw) as pctx:
+        pctx.profile(reset=True)
+        serve.replay(pctx, requests(prof_in, at_once=True), rounds_per_step)
+        torch.cuda.synchronize()
+        prof = pctx.profile(reset=True)
+    del prof_in
+    # bit-exactness: results of the live and capacity runs agree everywhere;
+    # the oracle checks the smallest requests
+    same = all(torch.equal(a, b) for a, b in zip(live, full))
+    order = sorted(range(len(jobs)), key=lambda i: jobs[i].h * jobs[i].w)
+    exact = same
+    for i in order[:10]:
+        F = pristine[i].cpu().numpy()
+        ref = oracle.sweep_dirty(F, jobs[i].lam, jobs[i].adj)
+        st = rep.stats[i]
+        exact &= bool(np.array_equal(live[i].cpu().numpy(), ref.image))
+        exact &= (st.passes, st.lowerings) == (ref.passes, ref.lowerings)
+    alg = sum(2 * (1 if j.dtype == synth.U8 else 2) * j.h * j.w * cap.stats[i].passes
+              for i, j in enumerate(jobs))
+    kernel_s = prof.kernel_ms / 1e3
+    achieved = alg / kernel_s / 1e9 if kernel_s > 0 else None
+    out = {
+        "metric": METRIC,
+        "value": round(rep.mpixel_per_s, 3),
+        "unit": "Mpixel/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(rep.wall_s * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8+u16", "data": "synthetic",
+        "config": {"workload": "serving_poisson", "rate_per_s": rate, "trace_s": seconds,
+                   "requests": len(jobs), "sides": "log-uniform 64..4096",
+                   "dtypes": "u8/u16 1:1", "lambda": "uniform 0..50", "adjacency": "8,4",
+                   "rounds_per_step": rounds_per_step, "budget_bytes": budget_gib << 30,
+                   "path": "serving (thin_serve_admit / thin_serve_step)"},
+        "images_per_s": round(rep.images_per_s, 2),
+        "latency_ms_p50": round(rep.percentile_ms(50), 3),
+        "latency_ms_p99": round(rep.percentile_ms(99), 3),
+        "latency_ms_max": round(rep.percentile_ms(100), 3),
+        "max_resident": rep.max_resident,
+        "serve_steps": rep.steps,
+        "capacity_images_per_s": round(cap.images_per_s, 2),
+        "capacity_mpixel_per_s": round(cap.mpixel_per_s, 3),
+        "bit_exact_sample": exact,
+        "roofline": {
+            "bound": "hbm", "kernel": "k_round",
+            "achieved": round(achieved, 2) if achieved else None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": None,
+            "launches": int(prof.launches),
+            "avg_launch_us": round(prof.kernel_ms * 1e3 / max(prof.launches, 1), 3),
+            "timing": "HIP events around every round launch of a profiled capacity pass",
+        },
+    }
+    if cpu_s > 0:
+        smalls = [(pristine[i].cpu().numpy(), jobs[i].lam, jobs[i].adj) for i in order[:200]]
+        v, n, dt = cpu_baseline(smalls, cpu_s)
+        out["cpu_baseline"] = {"value": round(v, 4), "unit": "Mpixel/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"ORACLE-SWEEP-DIRTY, single-thread C, {n} of the "
+                                         f"trace's requests (smallest first) in {dt:.1f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,7 +428,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ridges_512",
                     choices=["ridges_512", "blobs_128", "blobs_8192_u16", "batch_512",
-                             "copy_calibration"])
+                             "serving", "copy_calibration"])
+    ap.add_argument("--serve-seconds", type=float, default=1.0,
+                    help="length of the serving trace (Poisson arrivals at 2000/s)")
+    ap.add_argument("--serve-rounds", type=int, default=2,
+                    help="round launches per serving step")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU budget of the oracle baseline (0 disables it)")
     ap.add_argument("--tile", type=int, default=0)
@@ -339,7 +454,10 @@ def main():
     if args.workload == "copy_calibration":
         print(json.dumps(copy_calibration()), flush=True)
         return
-    if args.workload == "batch_512":
+    if args.workload == "serving":
+        out = bench_serving(args.cpu_seconds, args.tile, args.k, args.serve_seconds,
+                            rounds_per_step=args.serve_rounds)
+    elif args.workload == "batch_512":
         out = bench_batch(args.steps, args.warmup, args.cpu_seconds, args.tile, args.k,
                           args.engine)
     else:

@@ -138,19 +138,31 @@ int thin_run(thin_ctx* ctx, void* image, int64_t h, int64_t w, int32_t dtype,
  * and statistics equal those of a thin_run call on it alone. */
 int thin_run_batch(thin_ctx* ctx, const thin_image* imgs, int32_t n, thin_stats* stats);
 
-/* Serving (continuous batching).  thin_serve_admit makes an image resident
- * under a caller-chosen tag; it starts at the next round.  Returns THIN_EBUSY,
- * leaving nothing admitted, when its scratch would exceed max_device_bytes.
- * The image buffer must stay valid until the tag is retired. */
+/* Serving (continuous batching) of independent images, each lowered exactly
+ * as thin_run would lower it alone (section 2.2, lambda-destructible type
+ * set; section 2.1 for the test and alpha-).  thin_serve_admit makes an
+ * image resident under a caller-chosen tag; it takes part from the next
+ * round of thin_serve_step on, each image on its own round clock.  The
+ * first admission reserves the serving budget once: max_device_bytes when
+ * set, else 1 GiB (twins take about 29/32 of it, per-tile state the rest)
+ * and at most 16384 images are resident at a time.  An image whose twin or
+ * tile state does not fit next to the resident ones is refused with
+ * THIN_EBUSY and nothing is admitted: step and admit again later.  Images
+ * smaller than 3x3 retire at the next thin_serve_step unchanged.  The image
+ * buffer must stay valid, and untouched by the caller, until its tag is
+ * reported.  Serving needs the tiled or cooperative engine setting
+ * (THIN_EINVAL otherwise); it always runs the tiled round kernel. */
 int thin_serve_admit(thin_ctx* ctx, const thin_image* img, uint64_t tag);
 
-/* Runs `rounds` rounds over every resident image, then retires the images
- * that are stable (or hit max_passes): their final values are in their own
- * buffers when the call returns.  Up to `cap` retired tags are written to
- * done_tags (and their statistics to done_stats when not NULL); *n_done
- * receives how many were written.  Images beyond `cap` stay resident and are
- * reported by a later call.  *n_resident (nullable) receives the number of
- * images still resident. */
+/* Runs `rounds` round launches (each up to steps_per_round parity steps of
+ * every active tile) over every resident image, then retires the images that
+ * are stable (or reached max_passes): their final values are in their own
+ * buffers when the call returns.  rounds may be 0 to only collect reports.
+ * Up to `cap` retired tags, oldest first, are written to done_tags (and their
+ * statistics to done_stats when not NULL); *n_done (nullable) receives how
+ * many were written; the rest are reported by later calls.  *n_resident
+ * (nullable) receives the number of images still resident.  Blocks until the
+ * launched rounds are done. */
 int thin_serve_step(thin_ctx* ctx, int32_t rounds, uint64_t* done_tags, thin_stats* done_stats,
                     int32_t cap, int32_t* n_done, int32_t* n_resident);
 

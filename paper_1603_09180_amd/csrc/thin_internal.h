@@ -24,6 +24,9 @@ struct ImgDev {
     int32_t max_steps;   // parity-step cap (4 * max_passes), INT32_MAX if none
     int32_t ring0;       // persistent engine: first entry of its round-completion ring
     int32_t ring_w;      // ring length (> largest round spread between its tiles)
+    int32_t slot;        // index of its counters (stable while the image is resident)
+    int32_t pad;
+    int64_t state0;      // index of its first tile in the per-tile state array
 };
 
 // Per-image counters, written by the kernels with device-scope atomics.

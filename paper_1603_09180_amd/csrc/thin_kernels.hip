@@ -450,6 +450,8 @@ __device__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
     if (nsteps <= 0) return 0;
     const int lt = g - d->tile0;
     const int ty = lt / d->tiles_x, tx = lt - ty * d->tiles_x;
+    const int slot = d->slot;
+    int32_t* st = tile_state + 2 * (d->state0 + lt);  // this tile's state pair
 
     // tile_state[2g] is the latest round for which a tile of g's 3x3 tile
     // neighbourhood asked g to be active (it lowered something during the
@@ -461,9 +463,9 @@ __device__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
     // readers.
     int vote = 0;
     if (tid == 0) {
-        const int act = __hip_atomic_load(&tile_state[2 * g], __ATOMIC_RELAXED,
+        const int act = __hip_atomic_load(&st[0], __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
-        const int chg = __hip_atomic_load(&tile_state[2 * g + 1], __ATOMIC_RELAXED,
+        const int chg = __hip_atomic_load(&st[1], __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
         vote = (r == 0 || act >= r) ? 1 : (chg == r - 1 ? 2 : 0);
     }
@@ -498,12 +500,11 @@ __device__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                              SEED ? &sd : nullptr, s_lut + d->adj * 256, s_count, s_last, tid,
                              last_tau);
     if (tid == 0) {
-        atomicAdd(&cnt[ii].tile_rounds, 1ull);
+        atomicAdd(&cnt[slot].tile_rounds, 1ull);
         if (last_tau >= 0) {
-            __hip_atomic_store(&tile_state[2 * g + 1], r, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            atomicAdd(&cnt[ii].lowerings, (unsigned long long)count);
-            atomicMax(&cnt[ii].last_step, t0 + last_tau);
+            __hip_atomic_store(&st[1], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            atomicAdd(&cnt[slot].lowerings, (unsigned long long)count);
+            atomicMax(&cnt[slot].last_step, t0 + last_tau);
         }
         // Lowered during the last 4 steps: the 3x3 tile block must run the next
         // round (a tile whose whole block was quiet for 4 steps cannot change
@@ -515,7 +516,7 @@ __device__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                 for (int dx = -1; dx <= 1; ++dx) {
                     const int x = tx + dx;
                     if (x < 0 || x >= d->tiles_x) continue;
-                    __hip_atomic_fetch_max(&tile_state[2 * (d->tile0 + y * d->tiles_x + x)],
+                    __hip_atomic_fetch_max(&tile_state[2 * (d->state0 + y * d->tiles_x + x)],
                                            r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
             }

@@ -18,6 +18,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <iterator>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -37,14 +39,72 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// First-fit allocator of offsets inside one device buffer (host bookkeeping).
+class Arena {
+public:
+    void reset(uint64_t cap)
+    {
+        cap_ = cap;
+        free_.clear();
+        if (cap) free_[0] = cap;
+    }
+    uint64_t capacity() const { return cap_; }
+    // Returns an offset aligned to `align`, or UINT64_MAX when nothing fits.
+    uint64_t alloc(uint64_t len, uint64_t align)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            const uint64_t start = (it->first + align - 1) / align * align;
+            const uint64_t end = it->first + it->second;
+            if (start + len > end) continue;
+            const uint64_t f0 = it->first;
+            free_.erase(it);
+            if (start > f0) free_[f0] = start - f0;
+            if (end > start + len) free_[start + len] = end - (start + len);
+            return start;
+        }
+        return UINT64_MAX;
+    }
+    void release(uint64_t off, uint64_t len)
+    {
+        auto it = free_.emplace(off, len).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+private:
+    uint64_t cap_ = 0;
+    std::map<uint64_t, uint64_t> free_;
+};
+
 struct Resident {          // one image admitted for serving
     thin_image img;
     uint64_t tag;
-    int round0;            // launch round of its first step
-    size_t twin_off;       // offset of its twin inside the serving arena
-    size_t twin_bytes;
+    int round0;            // launch round of its first parity step
+    uint64_t twin_off, twin_len;    // its twin inside the twin arena
+    uint64_t state_off, ntiles;     // its per-tile state inside the state arena (tiles)
+    int tiles_x, tiles_y;
+    int slot;              // its counters
     int max_steps;
+    bool fresh;            // state not yet initialised on the device
 };
+
+struct Retired {
+    uint64_t tag;
+    thin_stats stats;
+};
+
+constexpr int kServeSlots = 1 << 14;          // resident images at most
+constexpr uint64_t kServeDefaultBudget = 1ull << 30;
 
 }  // namespace
 
@@ -73,12 +133,18 @@ struct thin_ctx {
     double prof_ms = 0.0;
     uint64_t prof_tile_rounds = 0;
 
-    // serving
+    // serving (continuous batching)
     std::vector<Resident> resident;
-    int serve_round = 0;
-    DevBuf serve_twin;
-    size_t serve_twin_used = 0;
-    uint64_t serve_bytes = 0;      // footprint of resident images
+    std::vector<Retired> retired;  // finished, not yet reported
+    std::vector<int> free_slots;
+    int serve_round = 0;           // next launch round of the serving clock
+    bool serve_ready = false;
+    bool serve_dirty = true;       // resident set changed since the device list was built
+    int serve_ntiles = 0;          // entries of the device tile list
+    TileShape serve_shape{0, 0, 0, 0, false};
+    Arena twin_arena, state_arena;
+    DevBuf serve_twin, serve_state, serve_cnt, serve_imgs, serve_tile_img;
+    ImgCnt* serve_snap = nullptr;  // pinned copy of all counter slots
 
     std::string last_error;
 };
@@ -278,6 +344,8 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
         d.tile0 = (int32_t)plan.tile_img.size();
         d.round0 = 0;
         d.max_steps = max_steps;
+        d.slot = (int32_t)plan.imgs.size();
+        d.state0 = d.tile0;
         const int64_t nt = (int64_t)d.tiles_x * d.tiles_y;
         if ((int64_t)plan.tile_img.size() + nt > INT_MAX / 2)
             return fail(ctx, THIN_EINVAL, "too many tiles in one call");
@@ -424,6 +492,8 @@ int run_coop(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
         d.tile0 = (int32_t)plan.tile_img.size();
         d.round0 = 0;
         d.max_steps = max_steps;
+        d.slot = (int32_t)plan.imgs.size();
+        d.state0 = d.tile0;
         const int64_t nt = (int64_t)d.tiles_x * d.tiles_y;
         if ((int64_t)plan.tile_img.size() + nt > INT_MAX / 2)
             return fail(ctx, THIN_EINVAL, "too many tiles in one call");
@@ -548,6 +618,8 @@ int run_persist(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& wo
         d.round0 = 0;
         d.max_steps = max_steps;
         d.ring_w = std::max(d.tiles_x, d.tiles_y) + 3;
+        d.slot = (int32_t)imgs.size();
+        d.state0 = d.tile0;
         d.ring0 = nring;
         nring += d.ring_w;
         const int64_t nt = (int64_t)d.tiles_x * d.tiles_y;
@@ -813,9 +885,10 @@ int thin_destroy(thin_ctx* ctx)
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
-    DevBuf* bufs[] = {&ctx->twin,     &ctx->imgs,      &ctx->cnt,        &ctx->tile_img,
-                      &ctx->tile_last, &ctx->progress, &ctx->ring,       &ctx->sched,
-                      &ctx->hist_bits, &ctx->hist_round, &ctx->serve_twin};
+    DevBuf* bufs[] = {&ctx->twin,       &ctx->imgs,        &ctx->cnt,        &ctx->tile_img,
+                      &ctx->tile_last,  &ctx->progress,    &ctx->ring,       &ctx->sched,
+                      &ctx->hist_bits,  &ctx->hist_round,  &ctx->serve_twin, &ctx->serve_state,
+                      &ctx->serve_cnt,  &ctx->serve_imgs,  &ctx->serve_tile_img};
     for (DevBuf* b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->d_lut) (void)hipFree(ctx->d_lut);
@@ -824,6 +897,7 @@ int thin_destroy(thin_ctx* ctx)
         if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
     }
     for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
+    if (ctx->serve_snap) (void)hipHostFree(ctx->serve_snap);
     delete ctx;
     return THIN_OK;
 }
@@ -875,21 +949,204 @@ int thin_topology_table(int32_t adjacency, uint32_t* out, int32_t n)
 
 int thin_serve_admit(thin_ctx* ctx, const thin_image* img, uint64_t tag)
 {
-    (void)img;
-    (void)tag;
-    return fail(ctx, THIN_EINVAL, "serving is not available yet");
+    if (!ctx) return THIN_EINVAL;
+    if (!img) return fail(ctx, THIN_EINVAL, "NULL image descriptor");
+    int rc = validate(ctx, *img);
+    if (rc) return rc;
+    if (ctx->engine == THIN_ENGINE_STEP || ctx->engine == THIN_ENGINE_PERSIST)
+        return fail(ctx, THIN_EINVAL, "serving runs on the tiled engine");
+    if (img->h < 3 || img->w < 3) {
+        Retired d{tag, {}};
+        fill_stats(&d.stats, ImgCnt{}, 0, 0, true);
+        ctx->retired.push_back(d);
+        return THIN_OK;
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (!ctx->serve_ready) {
+        TileShape shape = choose_shape(ctx, 0);
+        if (shape.seed) shape = TileShape{shape.th, shape.tw, shape.k, shape.nt, false};
+        if (!thin::tile_shape_supported(shape))
+            return fail(ctx, THIN_EINVAL, "no compiled serving shape %dx%d k=%d", shape.th,
+                        shape.tw, shape.k);
+        // The serving budget (max_device_bytes, else kServeDefaultBudget) is
+        // split once: counters and descriptors for kServeSlots images, 1/32
+        // for tile state (8 bytes a tile), 1/64 for the tile list (4 bytes a
+        // tile), the rest for twins.
+        const uint64_t budget = ctx->max_device_bytes ? ctx->max_device_bytes : kServeDefaultBudget;
+        const uint64_t fixed = (sizeof(ImgCnt) + sizeof(ImgDev)) * (uint64_t)kServeSlots;
+        const uint64_t state_cap = budget / 32, list_cap = budget / 64;
+        if (budget < 2 * (fixed + (1u << 20)))
+            return fail(ctx, THIN_ENOMEM, "serving needs max_device_bytes of at least %llu",
+                        (unsigned long long)(2 * (fixed + (1u << 20))));
+        const uint64_t twin_cap = budget - fixed - state_cap - list_cap;
+        if ((rc = ensure(ctx, ctx->serve_twin, twin_cap))) return rc;
+        if ((rc = ensure(ctx, ctx->serve_state, state_cap))) return rc;
+        if ((rc = ensure(ctx, ctx->serve_tile_img, list_cap))) return rc;
+        if ((rc = ensure(ctx, ctx->serve_cnt, sizeof(ImgCnt) * kServeSlots))) return rc;
+        if ((rc = ensure(ctx, ctx->serve_imgs, sizeof(ImgDev) * kServeSlots))) return rc;
+        if (hipHostMalloc((void**)&ctx->serve_snap, sizeof(ImgCnt) * kServeSlots,
+                          hipHostMallocDefault) != hipSuccess)
+            return fail(ctx, THIN_ENOMEM, "hipHostMalloc of serving counters failed");
+        ctx->twin_arena.reset(twin_cap);
+        ctx->state_arena.reset(std::min(state_cap / (2 * sizeof(int32_t)),
+                                        list_cap / sizeof(int32_t)));
+        ctx->free_slots.clear();
+        for (int i = kServeSlots - 1; i >= 0; --i) ctx->free_slots.push_back(i);
+        ctx->serve_shape = shape;
+        ctx->serve_ready = true;
+    }
+    const TileShape shape = ctx->serve_shape;
+    Resident r{};
+    r.img = *img;
+    if (!r.img.pitch_elems) r.img.pitch_elems = r.img.w;
+    r.tag = tag;
+    r.round0 = ctx->serve_round;
+    const uint64_t bpp = img->dtype == THIN_U8 ? 1 : 2;
+    r.twin_len = (uint64_t)img->h * (uint64_t)r.img.pitch_elems * bpp;
+    r.tiles_y = (int)((img->h + shape.th - 1) / shape.th);
+    r.tiles_x = (int)((img->w + shape.tw - 1) / shape.tw);
+    r.ntiles = (uint64_t)r.tiles_x * r.tiles_y;
+    r.max_steps = steps_cap(ctx);
+    r.fresh = true;
+    if (ctx->free_slots.empty())
+        return fail(ctx, THIN_EBUSY, "all %d serving slots are in use", kServeSlots);
+    r.twin_off = ctx->twin_arena.alloc(r.twin_len, 256);
+    if (r.twin_off == UINT64_MAX)
+        return fail(ctx, THIN_EBUSY, "image of %llu bytes does not fit the serving budget",
+                    (unsigned long long)r.twin_len);
+    r.state_off = ctx->state_arena.alloc(r.ntiles, 1);
+    if (r.state_off == UINT64_MAX) {
+        ctx->twin_arena.release(r.twin_off, r.twin_len);
+        return fail(ctx, THIN_EBUSY, "tile state of the image does not fit the serving budget");
+    }
+    r.slot = ctx->free_slots.back();
+    ctx->free_slots.pop_back();
+    ctx->resident.push_back(r);
+    ctx->serve_dirty = true;
+    return THIN_OK;
 }
 
 int thin_serve_step(thin_ctx* ctx, int32_t rounds, uint64_t* done_tags, thin_stats* done_stats,
                     int32_t cap, int32_t* n_done, int32_t* n_resident)
 {
-    (void)rounds;
-    (void)done_tags;
-    (void)done_stats;
-    (void)cap;
     if (n_done) *n_done = 0;
-    if (n_resident) *n_resident = 0;
-    return fail(ctx, THIN_EINVAL, "serving is not available yet");
+    if (!ctx) return THIN_EINVAL;
+    if (rounds < 0 || cap < 0 || (cap > 0 && !done_tags))
+        return fail(ctx, THIN_EINVAL, "bad serve_step arguments");
+    int rc;
+    if (!ctx->resident.empty() && rounds > 0) {
+        HIP_TRY(ctx, hipSetDevice(ctx->device));
+        const TileShape shape = ctx->serve_shape;
+        const int K = shape.k;
+        ImgCnt* d_cnt = static_cast<ImgCnt*>(ctx->serve_cnt.ptr);
+        int32_t* d_state = static_cast<int32_t*>(ctx->serve_state.ptr);
+        // New residents: counters and tile state start empty (-1 everywhere).
+        for (Resident& r : ctx->resident) {
+            if (!r.fresh) continue;
+            ImgCnt c{0ull, 0ull, -1, -1};
+            ctx->serve_snap[r.slot] = c;
+            HIP_TRY(ctx, hipMemcpyAsync(d_cnt + r.slot, &ctx->serve_snap[r.slot], sizeof c,
+                                        hipMemcpyHostToDevice, ctx->stream));
+            HIP_TRY(ctx, hipMemsetAsync(d_state + 2 * r.state_off, 0xFF,
+                                        2 * sizeof(int32_t) * r.ntiles, ctx->stream));
+            r.fresh = false;
+        }
+        if (ctx->serve_dirty) {
+            // Descriptors and the tile list of the current residents; an
+            // image keeps its round clock, counters and tile state across
+            // rebuilds, so only its position in the lists changes.
+            std::vector<ImgDev> imgs;
+            std::vector<int32_t> tile_img;
+            for (const Resident& r : ctx->resident) {
+                ImgDev d{};
+                d.buf[0] = r.img.image;
+                d.buf[1] = static_cast<char*>(ctx->serve_twin.ptr) + r.twin_off;
+                d.pitch = r.img.pitch_elems;
+                d.h = (int32_t)r.img.h;
+                d.w = (int32_t)r.img.w;
+                d.dtype = r.img.dtype;
+                d.lambda = r.img.lambda;
+                d.adj = r.img.adjacency;
+                d.tiles_x = r.tiles_x;
+                d.tiles_y = r.tiles_y;
+                d.tile0 = (int32_t)tile_img.size();
+                d.round0 = r.round0;
+                d.max_steps = r.max_steps;
+                d.slot = r.slot;
+                d.state0 = (int64_t)r.state_off;
+                for (uint64_t t = 0; t < r.ntiles; ++t) tile_img.push_back((int32_t)imgs.size());
+                imgs.push_back(d);
+            }
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->serve_imgs.ptr, imgs.data(), sizeof(ImgDev) * imgs.size(),
+                                        hipMemcpyHostToDevice, ctx->stream));
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->serve_tile_img.ptr, tile_img.data(),
+                                        sizeof(int32_t) * tile_img.size(), hipMemcpyHostToDevice,
+                                        ctx->stream));
+            // The host vectors are released at scope end: wait for the copies.
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+            ctx->serve_ntiles = (int)tile_img.size();
+            ctx->serve_dirty = false;
+        }
+        const int ntiles = ctx->serve_ntiles;
+        const int grid = ctx->num_cus * thin::round_blocks_per_cu(shape);
+        size_t ev_used = 0;
+        for (int k = 0; k < rounds; ++k) {
+            if ((rc = timed_round(ctx, ev_used, shape, static_cast<ImgDev*>(ctx->serve_imgs.ptr),
+                                  d_cnt, static_cast<int32_t*>(ctx->serve_tile_img.ptr), d_state,
+                                  ntiles, ctx->serve_round + k, grid,
+                                  static_cast<uint32_t*>(ctx->hist_bits.ptr),
+                                  static_cast<int32_t*>(ctx->hist_round.ptr))))
+                return rc;
+        }
+        ctx->serve_round += rounds;
+        int max_slot = 0;
+        for (const Resident& r : ctx->resident) max_slot = std::max(max_slot, r.slot + 1);
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->serve_snap, d_cnt, sizeof(ImgCnt) * max_slot,
+                                    hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        if (ctx->profile && (rc = collect_profile(ctx, ev_used))) return rc;
+        // Retire stable images (or images at their pass cap).
+        std::vector<Resident> keep;
+        for (const Resident& r : ctx->resident) {
+            const ImgCnt& c = ctx->serve_snap[r.slot];
+            const int cap_rounds = r.max_steps == INT_MAX ? INT_MAX : (r.max_steps + K - 1) / K;
+            const int r_img = std::min(ctx->serve_round - r.round0, cap_rounds);
+            const int steps = (int)std::min<int64_t>((int64_t)r_img * K, r.max_steps);
+            const bool stable = c.last_step < steps - 4;
+            if (!stable && steps < r.max_steps) {
+                keep.push_back(r);
+                continue;
+            }
+            if (r_img & 1) {
+                const size_t bpp = r.img.dtype == THIN_U8 ? 1 : 2;
+                const size_t pitch = (size_t)r.img.pitch_elems * bpp;
+                HIP_TRY(ctx, hipMemcpy2DAsync(r.img.image, pitch,
+                                              static_cast<char*>(ctx->serve_twin.ptr) + r.twin_off,
+                                              pitch, (size_t)r.img.w * bpp, (size_t)r.img.h,
+                                              hipMemcpyDeviceToDevice, ctx->stream));
+            }
+            if (ctx->profile) ctx->prof_tile_rounds += c.tile_rounds;
+            Retired d{r.tag, {}};
+            fill_stats(&d.stats, c, steps, r.max_steps, false);
+            ctx->retired.push_back(d);
+            ctx->twin_arena.release(r.twin_off, r.twin_len);
+            ctx->state_arena.release(r.state_off, r.ntiles);
+            ctx->free_slots.push_back(r.slot);
+            ctx->serve_dirty = true;
+        }
+        ctx->resident.swap(keep);
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    // Report retired images, oldest first.
+    const int n = std::min<int>(cap, (int)ctx->retired.size());
+    for (int i = 0; i < n; ++i) {
+        done_tags[i] = ctx->retired[i].tag;
+        if (done_stats) done_stats[i] = ctx->retired[i].stats;
+    }
+    ctx->retired.erase(ctx->retired.begin(), ctx->retired.begin() + n);
+    if (n_done) *n_done = n;
+    if (n_resident) *n_resident = (int32_t)ctx->resident.size();
+    return THIN_OK;
 }
 
 }  // extern "C"

@@ -194,3 +194,38 @@ def random_small(seed: int, max_side: int = 40, levels: int = 256, dtype=U8):
     if np.dtype(dtype) == np.uint16:
         f = f * 257 if levels == 256 else f
     return f.astype(dtype)
+
+
+def gen_blobs_device(h: int, w: int, seed: int, dtype=U8, device="cuda", nblobs: int = 12,
+                     sigma=(4.0, 16.0), amplitude=(40.0, 200.0), noise: float = 10.0):
+    """gen_blobs's recipe drawn on the GPU, for workloads too large to draw
+    on the host (thousands of images up to 4096x4096).
+
+    Blob centres, widths and amplitudes come from the same numpy stream as in
+    gen_blobs; the noise comes from torch's generator seeded with `seed`, so
+    the pixels differ from gen_blobs(h, w, seed) while the distribution is the
+    same.  Returns a 2-D uint8/uint16 tensor on `device`.
+    """
+    import torch
+
+    rng = np.random.default_rng(seed)
+    rows = torch.arange(h, dtype=torch.float64, device=device)
+    cols = torch.arange(w, dtype=torch.float64, device=device)
+    f = torch.zeros((h, w), dtype=torch.float64, device=device)
+    for _ in range(nblobs):
+        ci = rng.uniform(0.0, h)
+        cj = rng.uniform(0.0, w)
+        s = rng.uniform(sigma[0], sigma[1]) if isinstance(sigma, (tuple, list)) else float(sigma)
+        a = rng.uniform(amplitude[0], amplitude[1])
+        gi = torch.exp(-((rows - ci) ** 2) / (2.0 * s * s))
+        gj = torch.exp(-((cols - cj) ** 2) / (2.0 * s * s))
+        f += a * torch.outer(gi, gj)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    f += (torch.rand((h, w), dtype=torch.float64, device=device, generator=g) * 2.0 - 1.0) * noise
+    f.clamp_(0.0, 255.0)
+    if np.dtype(dtype) == np.uint8:
+        return torch.round(f).to(torch.uint8)
+    if np.dtype(dtype) == np.uint16:
+        return torch.round(f * 257.0).to(torch.int32).to(torch.uint16)
+    raise ValueError(f"unsupported dtype {dtype}")

@@ -253,6 +253,7 @@ class Context:
         self.device = device
         self.stream = stream
         self.handle = thin_create(cfg)
+        self._serve_bufs = None
 
     def close(self):
         if self.handle:
@@ -296,6 +297,31 @@ class Context:
         rc = thin_run_batch(self.handle, arr, n, st)
         self._check(rc, "thin_run_batch", allow_limit)
         return [Stats.of(st[i]) for i in range(n)]
+
+    # ---------------------------------------------------------- serving
+
+    def serve_admit(self, t, lam: int, adj="8,4", tag: int = 0) -> bool:
+        """Makes device tensor `t` resident for serving under `tag`; False
+        when the serving budget is full (nothing admitted)."""
+        im = describe(t, lam, adj)
+        rc = thin_serve_admit(self.handle, im, tag)
+        if rc == THIN_EBUSY:
+            return False
+        self._check(rc, "thin_serve_admit")
+        return True
+
+    def serve_step(self, rounds: int, cap: int = 4096):
+        """Runs `rounds` rounds over the resident images; returns
+        ([(tag, Stats), ...] of the retired ones, number still resident)."""
+        if self._serve_bufs is None or len(self._serve_bufs[0]) < cap:
+            self._serve_bufs = ((ctypes.c_uint64 * cap)(), (thin_stats * cap)())
+        tags, sts = self._serve_bufs
+        n_done = ctypes.c_int32(0)
+        n_res = ctypes.c_int32(0)
+        rc = thin_serve_step(self.handle, rounds, tags, sts, cap, ctypes.byref(n_done),
+                             ctypes.byref(n_res))
+        self._check(rc, "thin_serve_step")
+        return [(int(tags[i]), Stats.of(sts[i])) for i in range(n_done.value)], n_res.value
 
 
 def run(t, lam: int, adj="8,4", **kw) -> Stats:
