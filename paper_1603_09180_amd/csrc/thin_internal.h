@@ -22,10 +22,7 @@ struct ImgDev {
     int32_t tile0;       // index of its first tile in the launch's tile arrays
     int32_t round0;      // launch round at which the image's step 0 starts
     int32_t max_steps;   // parity-step cap (4 * max_passes), INT32_MAX if none
-    int32_t ring0;       // persistent engine: first entry of its round-completion ring
-    int32_t ring_w;      // ring length (> largest round spread between its tiles)
     int32_t slot;        // index of its counters (stable while the image is resident)
-    int32_t pad;
     int64_t state0;      // index of its first tile in the per-tile state array
 };
 
@@ -34,14 +31,7 @@ struct ImgCnt {
     unsigned long long lowerings;
     unsigned long long tile_rounds;
     int32_t last_step;   // image-local index of the last step that lowered, -1 if none
-    int32_t final_round; // persistent engine: rounds after which the image is final, -1 before
-};
-
-// Scheduler state of one persistent launch.
-struct Sched {
-    unsigned long long next;   // work items handed out (item q = round q / ntiles, tile q % ntiles)
-    int32_t images_left;       // images not yet final
-    int32_t error;             // 1 when a dependency wait exceeded its time limit
+    int32_t pad;
 };
 
 // Connectivity table entry for an upper-neighbour mask (see thin_topology_table).
@@ -55,11 +45,17 @@ struct TopoEntry {
 // Host-side generation of the 2 x 256 table (adjacency-major).
 void build_topology_table(int adjacency, TopoEntry out[256]);
 
+// Residency variants.  kVarFlags keeps the tile in LDS with a re-examination
+// flag per pixel; kVarSeeded also starts those flags from the previous
+// round's change bitmaps; kVarRegs keeps each thread's 4x4 windows in
+// registers and tracks re-examination per window.
+constexpr int kVarFlags = 0, kVarSeeded = 1, kVarRegs = 2;
+
 // Tiled engine geometry chosen at run time among the compiled variants.
 struct TileShape {
     int th, tw, k;   // tile height, width, halo = parity steps per residency
     int nt;          // threads per tile
-    bool seed;       // residencies seed their dirty flags from the previous round
+    int var;         // residency variant: kVarFlags, kVarSeeded or kVarRegs
 };
 
 // The compiled shape with this tile and halo (nt = 0 when there is none).
@@ -76,20 +72,12 @@ hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs,
 int history_words(TileShape s);
 hipError_t launch_step(hipStream_t stream, const ImgDev* img_host, const ImgDev* img_dev,
                        ImgCnt* cnt, int step, const TopoEntry* lut);
-hipError_t launch_persist(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
-                          const int32_t* tile_img, int32_t* tile_last, int32_t* progress,
-                          int32_t* ring, Sched* sched, int ntiles, const TopoEntry* lut,
-                          int grid_blocks, unsigned long long wait_ticks,
-                          unsigned long long kernel_ticks);
+// Cooperative engine: every round in one launch, grid-wide barriers between
+// rounds.  active: 3 zeroed counters; rounds_out receives the rounds run.
 hipError_t launch_coop(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                        const int32_t* tile_img, int32_t* tile_last, int ntiles,
                        const TopoEntry* lut, int32_t* active, int32_t* rounds_out,
                        int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round);
-hipError_t launch_init_persist(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t* tile_last,
-                               int32_t* progress, int ntiles, int32_t* ring, int nring,
-                               Sched* sched);
-int persist_threads(TileShape s);
-int persist_blocks_per_cu(TileShape s);
 bool tile_shape_supported(TileShape s);
 int round_blocks_per_cu(TileShape s);
 

@@ -28,6 +28,7 @@
 #include "thin_internal.h"
 
 #include <climits>
+#include <type_traits>
 
 #include <hip/hip_cooperative_groups.h>
 
@@ -36,16 +37,23 @@ namespace thin {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int STAGE_CHUNK = 8;  // global loads in flight per thread while staging a tile
 
-// Decision and new value for one candidate; nb in ring order E, NE, N, NW,
-// W, SW, S, SE.  lut points at the 256 entries of the image's adjacency.
-__device__ __forceinline__ bool decide(uint32_t v, const uint32_t (&nb)[8], const TopoEntry* lut,
-                                       uint32_t lambda, uint32_t& alpha)
+// Upper-neighbour mask of a candidate of value v: bit p set when ring
+// neighbour p (order E, NE, N, NW, W, SW, S, SE) has a value >= v.
+__device__ __forceinline__ uint32_t upper_mask(uint32_t v, const uint32_t (&nb)[8])
 {
     uint32_t u = 0;
 #pragma unroll
     for (int p = 0; p < 8; ++p) u |= (uint32_t)(nb[p] >= v) << p;
-    const TopoEntry e = lut[u];
+    return u;
+}
+
+// Decision and new value for one candidate with upper mask u and its table
+// entry e = lut[u] (the entries of the image's adjacency).
+__device__ __forceinline__ bool decide_entry(uint32_t v, const uint32_t (&nb)[8], uint32_t u,
+                                             TopoEntry e, uint32_t lambda, uint32_t& alpha)
+{
     bool lower = (e.flags & 1u) != 0u;
     const uint32_t k = (e.flags >> 4) & 7u;  // T--
     if (!lower && lambda != 0u && k >= 2u) {
@@ -66,6 +74,15 @@ __device__ __forceinline__ bool decide(uint32_t v, const uint32_t (&nb)[8], cons
         alpha = a;
     }
     return lower;
+}
+
+// Decision and new value for one candidate; nb in ring order E, NE, N, NW,
+// W, SW, S, SE.  lut points at the 256 entries of the image's adjacency.
+__device__ __forceinline__ bool decide(uint32_t v, const uint32_t (&nb)[8], const TopoEntry* lut,
+                                       uint32_t lambda, uint32_t& alpha)
+{
+    const uint32_t u = upper_mask(v, nb);
+    return decide_entry(v, nb, u, lut[u], lambda, alpha);
 }
 
 __device__ __forceinline__ uint32_t load_px(const void* base, int dtype, int64_t idx)
@@ -91,7 +108,7 @@ __global__ void k_init_state(ImgCnt* cnt, int nimg, int32_t* tile_last, int ntil
         cnt[i].lowerings = 0ull;
         cnt[i].tile_rounds = 0ull;
         cnt[i].last_step = -1;
-        cnt[i].final_round = -1;
+        cnt[i].pad = -1;
     }
     if (tile_last && i < 2 * ntiles) tile_last[i] = -1;
 }
@@ -202,6 +219,8 @@ struct Tile {
     static constexpr int RH = TH + 2 * K;
     static constexpr int RW = TW + 2 * K;
     static constexpr int RWP = RW;  // LDS row pitch in elements
+    static constexpr int IMG_ELEMS = RH * RWP;    // LDS elements of the image tile
+    static constexpr int DIRTY_ELEMS = RH * RWP;  // LDS re-examination flags
     // lanes across a candidate row: next power of two >= RW/2, at most 64
     static constexpr int LAT_H = RH / 2, LAT_W = RW / 2;  // candidate lattice of one class
     static constexpr int PPT = (LAT_H * LAT_W + NT - 1) / NT;  // lattice cells per thread
@@ -253,7 +272,7 @@ struct Tile {
     // of that round can have changed its 3x3 since, so the 3x3 of each such
     // pixel is marked.  The region lies inside the 3x3 tile block (K <= tile
     // side / 2), so the neighbours' bitmaps hold every pixel that matters.
-    static __device__ int run(const View d, int gy0, int gx0, int t0, int nsteps,
+    static __device__ __forceinline__ int run(const View d, int gy0, int gx0, int t0, int nsteps,
                               const void* src, void* dst, uint16_t* s_img, uint8_t* s_dirty,
                               uint32_t* s_bits, uint32_t* s_cw, const Seed* sd,
                               const TopoEntry* lut, int* s_count, int* s_last, int tid,
@@ -270,24 +289,31 @@ struct Tile {
         // All global loads of the region are issued before the first one is
         // waited for.  Zeros outside the image are never read by a candidate:
         // every candidate is an interior pixel whose 3x3 lies inside the image.
+        // Loads are issued in chunks of up to STAGE_CHUNK per thread before
+        // the first is waited for (more in flight would cost registers that
+        // the steps need).
         constexpr int ITER = (RH * RW + NT - 1) / NT;
-        uint32_t vals[ITER];
+        constexpr int CH = ITER < STAGE_CHUNK ? ITER : STAGE_CHUNK;
+#pragma unroll 1
+        for (int k0 = 0; k0 < ITER; k0 += CH) {
+            uint32_t vals[CH];
 #pragma unroll
-        for (int k = 0; k < ITER; ++k) {
-            const int idx = tid + k * NT;
-            const int y = idx / RW, x = idx - y * RW;
-            const int gi = ry0 + y, gj = rx0 + x;
-            vals[k] = 0;
-            if (idx < RH * RW && gi >= 0 && gi < d.h && gj >= 0 && gj < d.w)
-                vals[k] = load_px(src, d.dtype, (int64_t)gi * d.pitch + gj);
-        }
+            for (int c = 0; c < CH; ++c) {
+                const int idx = tid + (k0 + c) * NT;
+                const int y = idx / RW, x = idx - y * RW;
+                const int gi = ry0 + y, gj = rx0 + x;
+                vals[c] = 0;
+                if (idx < RH * RW && gi >= 0 && gi < d.h && gj >= 0 && gj < d.w)
+                    vals[c] = load_px(src, d.dtype, (int64_t)gi * d.pitch + gj);
+            }
 #pragma unroll
-        for (int k = 0; k < ITER; ++k) {
-            const int idx = tid + k * NT;
-            const int y = idx / RW, x = idx - y * RW;
-            if (idx < RH * RW) {
-                s_img[y * RWP + x] = (uint16_t)vals[k];
-                s_dirty[y * RWP + x] = seeded ? 0 : 1;
+            for (int c = 0; c < CH; ++c) {
+                const int idx = tid + (k0 + c) * NT;
+                const int y = idx / RW, x = idx - y * RW;
+                if (idx < RH * RW) {
+                    s_img[y * RWP + x] = (uint16_t)vals[c];
+                    s_dirty[y * RWP + x] = seeded ? 0 : 1;
+                }
             }
         }
         __syncthreads();
@@ -337,22 +363,18 @@ struct Tile {
         // lattice cell (a, b) in class (si, sj) is region pixel
         // (2a + si, 2b + sj).  The exact region and the image interior only
         // mask cells out step by step.
-        int cell_r[PPT], cell_c[PPT];
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) {
-            const int idx = tid + k * NT;
-            cell_r[k] = idx < LAT_H * LAT_W ? (idx / LAT_W) * 2 : RH;  // RH: never in range
-            cell_c[k] = idx < LAT_H * LAT_W ? (idx % LAT_W) * 2 : 0;
-        }
         for (int tau = 0; tau < nsteps; ++tau) {
             const int s = (t0 + tau) & 3, si = s >> 1, sj = s & 1;
             // Exact region after tau steps, clipped to the image interior.
             const int r_lo = max(tau + 1, 1 - ry0), r_hi = min(RH - 2 - tau, d.h - 2 - ry0);
             const int c_lo = max(tau + 1, 1 - rx0), c_hi = min(RW - 2 - tau, d.w - 2 - rx0);
             bool inner = false;
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const int lr = cell_r[k] + si, lc = cell_c[k] + sj;
+            // The loop over the thread's cells stays rolled: unrolled, the
+            // compiler interleaves cells and runs out of registers.
+#pragma unroll 1
+            for (int idx = tid; idx < LAT_H * LAT_W; idx += NT) {
+                const int a = idx / LAT_W;
+                const int lr = 2 * a + si, lc = 2 * (idx - a * LAT_W) + sj;
                 if (lr < r_lo || lr > r_hi || lc < c_lo || lc > c_hi) continue;
                 const int o = lr * RWP + lc;
                 {
@@ -408,38 +430,233 @@ struct Tile {
     }
 };
 
-// Largest tile_last over the 3x3 tile neighbourhood of (ty, tx).
-__device__ __forceinline__ int32_t neighbourhood_last(const ImgDev* d, const int32_t* tile_last,
-                                                      int ty, int tx)
-{
-    const int tiles_x = d->tiles_x, tiles_y = d->tiles_y, tile0 = d->tile0;
-    int32_t m = INT_MIN;
-    for (int dy = -1; dy <= 1; ++dy) {
-        const int y = ty + dy;
-        if (y < 0 || y >= tiles_y) continue;
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int x = tx + dx;
-            if (x < 0 || x >= tiles_x) continue;
-            m = max(m, __hip_atomic_load(&tile_last[tile0 + y * tiles_x + x], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT));
+// Residency with register windows.  Each thread owns fixed cells of the 2x2
+// lattice of the region and keeps, per cell, the 4x4 window of pixels covered
+// by the 3x3 neighbourhoods of the cell's four candidates (one per parity
+// class).  A parity step changes only pixels of its class, which occupy four
+// window positions, one of them the cell's own candidate; so before each
+// step a thread re-reads from LDS the three positions of the previous step's
+// class that belong to other cells.  A candidate is examined only when a
+// pixel of its 3x3 changed since it was last examined (one bit per class and
+// cell, set by re-read values that differ and by the cell's own lowerings):
+// the re-examination rule of section 2.2, as in the flag variant.  LDS holds
+// the whole region as the exchange medium between cells and as the source of
+// the final interior store.
+template <int TH, int TW, int K, int NT>
+struct RTile {
+    static constexpr int RH = TH + 2 * K;
+    static constexpr int RW = TW + 2 * K;
+    static constexpr int RWP = RW + 2;                // a spare column on each side
+    static constexpr int IMG_ELEMS = (RH + 2) * RWP;  // a spare row above and below
+    static constexpr int DIRTY_ELEMS = 1;
+    static constexpr int LAT_H = RH / 2, LAT_W = RW / 2;
+    static constexpr int PPT = (LAT_H * LAT_W + NT - 1) / NT;  // lattice cells per thread
+    static constexpr int WPR = 1, BITS_WORDS = 1, CW_WORDS = 1;
+    static_assert(K % 4 == 0, "a residency must start at parity class 0");
+    static_assert(K <= TH && K <= TW, "halo must not exceed the tile side");
+    static_assert(TH % 2 == 0 && TW % 2 == 0, "tile sides must be even");
+
+    // LDS index of region pixel (y, x), y in [-1, RH], x in [-1, RW].
+    static __device__ __forceinline__ int at(int y, int x) { return (y + 1) * RWP + x + 1; }
+
+    // Classes whose candidate's 3x3 contains window position (i, j); the
+    // candidate of class (ci, cj) sits at (1 + ci, 1 + cj).
+    static constexpr uint32_t affect(int i, int j)
+    {
+        uint32_t m = 0;
+        for (int ci = 0; ci < 2; ++ci)
+            for (int cj = 0; cj < 2; ++cj)
+                if (ci <= i && i <= ci + 2 && cj <= j && j <= cj + 2) m |= 1u << (2 * ci + cj);
+        return m;
+    }
+
+    static __device__ void copy_interior(const View d, int gy0, int gx0, const void* src,
+                                         void* dst, int tid)
+    {
+        Tile<TH, TW, K, NT, false>::copy_interior(d, gy0, gx0, src, dst, tid);
+    }
+
+    struct Cells {
+        uint32_t win[PPT][16];  // 4x4 windows, row-major
+        int base[PPT];          // LDS index of window position (0, 0)
+        int cr[PPT], cc[PPT];   // region position of the cell's (0,0) candidate
+        uint32_t pend[PPT];     // bit c: the class-c candidate needs examining
+    };
+
+    // One parity step of class C (steps of a residency start at class 0).
+    template <int C>
+    static __device__ __forceinline__ void step(Cells& q, uint16_t* s_img, int tau, int r_lo,
+                                                int r_hi, int c_lo, int c_hi,
+                                                const TopoEntry* lut, uint32_t lambda,
+                                                int& my_count, bool& inner)
+    {
+        constexpr int si = C >> 1, sj = C & 1;
+        constexpr int P = (C + 3) & 3, pi = P >> 1, pj = P & 1;
+        if (tau > 0) {
+            // Window rows of class-P pixels are 1 - pi and 3 - pi, columns
+            // 1 - pj and 3 - pj; (1 + pi, 1 + pj) is the cell's own.
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+#pragma unroll
+                for (int di = 0; di < 2; ++di) {
+#pragma unroll
+                    for (int dj = 0; dj < 2; ++dj) {
+                        if (di == pi && dj == pj) continue;
+                        const int i = 1 - pi + 2 * di, j = 1 - pj + 2 * dj;
+                        const uint32_t nv = s_img[q.base[k] + i * RWP + j];
+                        if (nv != q.win[k][4 * i + j]) {
+                            q.win[k][4 * i + j] = nv;
+                            q.pend[k] |= affect(i, j);
+                        }
+                    }
+                }
+            }
+        }
+        constexpr int ci = 1 + si, cj = 1 + sj;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int lr = q.cr[k] + si, lc = q.cc[k] + sj;
+            if (lr < r_lo || lr > r_hi || lc < c_lo || lc > c_hi) continue;
+            if (((q.pend[k] >> C) & 1u) == 0u) continue;
+            q.pend[k] &= ~(1u << C);
+            uint32_t(&w)[16] = q.win[k];
+            const uint32_t nb[8] = {w[4 * ci + cj + 1],       w[4 * (ci - 1) + cj + 1],
+                                    w[4 * (ci - 1) + cj],     w[4 * (ci - 1) + cj - 1],
+                                    w[4 * ci + cj - 1],       w[4 * (ci + 1) + cj - 1],
+                                    w[4 * (ci + 1) + cj],     w[4 * (ci + 1) + cj + 1]};
+            uint32_t alpha;
+            if (decide(w[4 * ci + cj], nb, lut, lambda, alpha)) {
+                w[4 * ci + cj] = alpha;
+                s_img[q.base[k] + ci * RWP + cj] = (uint16_t)alpha;
+                q.pend[k] = 0xFu;
+                if (lr >= K && lr < K + TH && lc >= K && lc < K + TW) {
+                    ++my_count;
+                    inner = true;
+                }
+            }
         }
     }
-    return m;
-}
+
+    template <int C>
+    static __device__ __forceinline__ void full_step(Cells& q, const View& d, int ry0, int rx0,
+                                                     uint16_t* s_img, int tau,
+                                                     const TopoEntry* lut, int* s_last, int tid,
+                                                     int& my_count)
+    {
+        // Exact region after tau steps, clipped to the image interior.
+        const int r_lo = max(tau + 1, 1 - ry0), r_hi = min(RH - 2 - tau, d.h - 2 - ry0);
+        const int c_lo = max(tau + 1, 1 - rx0), c_hi = min(RW - 2 - tau, d.w - 2 - rx0);
+        bool inner = false;
+        step<C>(q, s_img, tau, r_lo, r_hi, c_lo, c_hi, lut, d.lambda, my_count, inner);
+        // One lane per wave that lowered an interior pixel records the step.
+        if (__ballot(inner) != 0ull && (tid & 63) == 0) atomicMax(s_last, tau);
+        __syncthreads();
+    }
+
+    // Same contract as Tile::run (history arguments unused).
+    static __device__ __forceinline__ int run(const View d, int gy0, int gx0, int t0, int nsteps,
+                              const void* src, void* dst, uint16_t* s_img, uint8_t*, uint32_t*,
+                              uint32_t*, const Seed*, const TopoEntry* lut, int* s_count,
+                              int* s_last, int tid, int& last_tau)
+    {
+        (void)t0;  // a multiple of 4: step tau has class tau mod 4
+        const int ry0 = gy0 - K, rx0 = gx0 - K;
+        if (tid == 0) {
+            *s_count = 0;
+            *s_last = -1;
+        }
+        constexpr int ITER = (RH * RW + NT - 1) / NT;
+        constexpr int CH = ITER < STAGE_CHUNK ? ITER : STAGE_CHUNK;
+        // spare rows and columns (read into windows, never used by a candidate)
+        for (int i = tid; i < 2 * RWP + 2 * RH; i += NT) {
+            int o;
+            if (i < RWP) o = i;
+            else if (i < 2 * RWP) o = (RH + 1) * RWP + (i - RWP);
+            else if (i < 2 * RWP + RH) o = (i - 2 * RWP + 1) * RWP;
+            else o = (i - 2 * RWP - RH + 1) * RWP + RWP - 1;
+            s_img[o] = 0;
+        }
+#pragma unroll 1
+        for (int k0 = 0; k0 < ITER; k0 += CH) {
+            uint32_t vals[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int idx = tid + (k0 + c) * NT;
+                const int y = idx / RW, x = idx - y * RW;
+                const int gi = ry0 + y, gj = rx0 + x;
+                vals[c] = 0;
+                if (idx < RH * RW && gi >= 0 && gi < d.h && gj >= 0 && gj < d.w)
+                    vals[c] = load_px(src, d.dtype, (int64_t)gi * d.pitch + gj);
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int idx = tid + (k0 + c) * NT;
+                const int y = idx / RW, x = idx - y * RW;
+                if (idx < RH * RW) s_img[at(y, x)] = (uint16_t)vals[c];
+            }
+        }
+        __syncthreads();
+
+        Cells q;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int idx = tid + k * NT;
+            const bool valid = idx < LAT_H * LAT_W;
+            const int a = valid ? idx / LAT_W : 0, b = valid ? idx % LAT_W : 0;
+            q.cr[k] = valid ? 2 * a : RH;  // RH: never in range
+            q.cc[k] = 2 * b;
+            q.base[k] = 2 * a * RWP + 2 * b;  // at(2a - 1, 2b - 1)
+            q.pend[k] = 0xFu;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t* row = reinterpret_cast<const uint32_t*>(s_img + q.base[k] + i * RWP);
+                const uint32_t w0 = row[0], w1 = row[1];
+                q.win[k][4 * i + 0] = w0 & 0xFFFFu;
+                q.win[k][4 * i + 1] = w0 >> 16;
+                q.win[k][4 * i + 2] = w1 & 0xFFFFu;
+                q.win[k][4 * i + 3] = w1 >> 16;
+            }
+        }
+
+        int my_count = 0;
+        for (int tau = 0; tau < nsteps; tau += 4) {
+            full_step<0>(q, d, ry0, rx0, s_img, tau, lut, s_last, tid, my_count);
+            if (tau + 1 < nsteps) full_step<1>(q, d, ry0, rx0, s_img, tau + 1, lut, s_last, tid, my_count);
+            if (tau + 2 < nsteps) full_step<2>(q, d, ry0, rx0, s_img, tau + 2, lut, s_last, tid, my_count);
+            if (tau + 3 < nsteps) full_step<3>(q, d, ry0, rx0, s_img, tau + 3, lut, s_last, tid, my_count);
+        }
+
+        const int ih = min(TH, d.h - gy0), iw = min(TW, d.w - gx0);
+        for (int idx = tid; idx < TH * TW; idx += NT) {
+            const int y = idx / TW, x = idx - y * TW;
+            if (y < ih && x < iw)
+                store_px(dst, d.dtype, (int64_t)(gy0 + y) * d.pitch + (gx0 + x),
+                         s_img[at(K + y, K + x)]);
+        }
+        if (my_count) atomicAdd(s_count, my_count);
+        __syncthreads();
+        last_tau = *s_last;
+        return *s_count;
+    }
+};
+
+template <int TH, int TW, int K, int NT, int VAR>
+using TileOf = typename std::conditional<VAR == kVarRegs, RTile<TH, TW, K, NT>,
+                                         Tile<TH, TW, K, NT, VAR == kVarSeeded>>::type;
 
 // ----------------------------------------------------------------- k_round
 
 // One tile of one round (launch-per-round and cooperative engines).
 // Returns 1 when the tile was processed (active), 0 when skipped.  All NT
 // threads must call it together.
-template <int TH, int TW, int K, int NT, bool SEED>
-__device__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
+template <int TH, int TW, int K, int NT, int VAR>
+__device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                           const int32_t* __restrict__ tile_img, int32_t* tile_state, int g,
                           int round, int ntiles, uint32_t* hist_bits, int32_t* hist_round,
                           uint16_t* s_img, uint8_t* s_dirty, uint32_t* s_bits, uint32_t* s_cw,
                           const TopoEntry* s_lut, int* s_count, int* s_last)
 {
-    using T = Tile<TH, TW, K, NT, SEED>;
+    using T = TileOf<TH, TW, K, NT, VAR>;
     const int tid = threadIdx.x;
     const int ii = tile_img[g];
     const ImgDev* d = imgs + ii;
@@ -483,7 +700,7 @@ __device__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
         return 0;
     }
     Seed sd{};
-    const int64_t words = SEED ? (int64_t)ntiles * TH * T::WPR : 0;
+    const int64_t words = VAR == kVarSeeded ? (int64_t)ntiles * TH * T::WPR : 0;
     sd.prev_bits = hist_bits + ((r + 1) & 1) * words;
     sd.prev_round = hist_round + ((r + 1) & 1) * ntiles;
     sd.cur_bits = hist_bits + (r & 1) * words;
@@ -497,7 +714,7 @@ __device__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
     sd.g = g;
     int last_tau;
     const int count = T::run(v, gy0, gx0, t0, nsteps, src, dst, s_img, s_dirty, s_bits, s_cw,
-                             SEED ? &sd : nullptr, s_lut + d->adj * 256, s_count, s_last, tid,
+                             VAR == kVarSeeded ? &sd : nullptr, s_lut + d->adj * 256, s_count, s_last, tid,
                              last_tau);
     if (tid == 0) {
         atomicAdd(&cnt[slot].tile_rounds, 1ull);
@@ -525,23 +742,23 @@ __device__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
     return 1;
 }
 
-template <int TH, int TW, int K, int NT, bool SEED>
+template <int TH, int TW, int K, int NT, int VAR>
 __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                                               const int32_t* __restrict__ tile_img,
                                               int32_t* tile_last, int ntiles, int round,
                                               const TopoEntry* __restrict__ lut_g,
                                               uint32_t* hist_bits, int32_t* hist_round)
 {
-    using T = Tile<TH, TW, K, NT, SEED>;
-    __shared__ uint16_t s_img[T::RH * T::RWP];
-    __shared__ uint8_t s_dirty[T::RH * T::RWP];
+    using T = TileOf<TH, TW, K, NT, VAR>;
+    __shared__ __align__(16) uint16_t s_img[T::IMG_ELEMS];
+    __shared__ uint8_t s_dirty[T::DIRTY_ELEMS];
     __shared__ uint32_t s_bits[T::BITS_WORDS];
     __shared__ uint32_t s_cw[T::CW_WORDS];
     __shared__ TopoEntry s_lut[512];
     __shared__ int s_count, s_last;
     for (int i = threadIdx.x; i < 512; i += NT) s_lut[i] = lut_g[i];
     for (int g = blockIdx.x; g < ntiles; g += gridDim.x)
-        round_tile<TH, TW, K, NT, SEED>(imgs, cnt, tile_img, tile_last, g, round, ntiles, hist_bits,
+        round_tile<TH, TW, K, NT, VAR>(imgs, cnt, tile_img, tile_last, g, round, ntiles, hist_bits,
                                   hist_round, s_img, s_dirty, s_bits, s_cw, s_lut, &s_count,
                                   &s_last);
 }
@@ -557,7 +774,7 @@ __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, I
 // grid barrier of round r and is cleared during round r + 2, after the next
 // barrier has proved those reads complete.
 
-template <int TH, int TW, int K, int NT, bool SEED>
+template <int TH, int TW, int K, int NT, int VAR>
 __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                                              const int32_t* __restrict__ tile_img,
                                              int32_t* tile_last, int ntiles,
@@ -565,9 +782,9 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
                                              int32_t* rounds_out, int max_rounds,
                                              uint32_t* hist_bits, int32_t* hist_round)
 {
-    using T = Tile<TH, TW, K, NT, SEED>;
-    __shared__ uint16_t s_img[T::RH * T::RWP];
-    __shared__ uint8_t s_dirty[T::RH * T::RWP];
+    using T = TileOf<TH, TW, K, NT, VAR>;
+    __shared__ __align__(16) uint16_t s_img[T::IMG_ELEMS];
+    __shared__ uint8_t s_dirty[T::DIRTY_ELEMS];
     __shared__ uint32_t s_bits[T::BITS_WORDS];
     __shared__ uint32_t s_cw[T::CW_WORDS];
     __shared__ TopoEntry s_lut[512];
@@ -582,7 +799,7 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
                                __HIP_MEMORY_SCOPE_AGENT);
         int mine = 0;
         for (int g = blockIdx.x; g < ntiles; g += gridDim.x)
-            mine += round_tile<TH, TW, K, NT, SEED>(imgs, cnt, tile_img, tile_last, g, round, ntiles,
+            mine += round_tile<TH, TW, K, NT, VAR>(imgs, cnt, tile_img, tile_last, g, round, ntiles,
                                               hist_bits, hist_round, s_img, s_dirty, s_bits, s_cw,
                                               s_lut, &s_count, &s_last);
         if (tid == 0 && mine) atomicAdd(&active[round % 3], mine);
@@ -597,7 +814,7 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
     if (blockIdx.x == 0 && tid == 0) *rounds_out = round + 1;
 }
 
-template <int TH, int TW, int K, int NT, bool SEED>
+template <int TH, int TW, int K, int NT, int VAR>
 hipError_t launch_coop_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                          const int32_t* tile_img, int32_t* tile_last, int ntiles,
                          const TopoEntry* lut, int32_t* active, int32_t* rounds_out,
@@ -605,7 +822,7 @@ hipError_t launch_coop_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
 {
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT, SEED>), NT, 0);
+        &per_cu, reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT, VAR>), NT, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     const int grid = max(1, min(ntiles, per_cu * num_cus));
@@ -613,231 +830,19 @@ hipError_t launch_coop_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                     (void*)&tile_last,  (void*)&ntiles,    (void*)&lut,
                     (void*)&active,     (void*)&rounds_out, (void*)&max_rounds,
                     (void*)&hist_bits,  (void*)&hist_round};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT, SEED>),
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT, VAR>),
                                       dim3(grid), dim3(NT), args, 0, stream);
 }
 
-template <int TH, int TW, int K, int NT, bool SEED>
+template <int TH, int TW, int K, int NT, int VAR>
 hipError_t launch_round_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                           const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
                           const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
                           int32_t* hist_round)
 {
     const int grid = max(1, min(ntiles, grid_blocks));
-    hipLaunchKernelGGL((k_round<TH, TW, K, NT, SEED>), dim3(grid), dim3(NT), 0, stream, imgs, cnt,
+    hipLaunchKernelGGL((k_round<TH, TW, K, NT, VAR>), dim3(grid), dim3(NT), 0, stream, imgs, cnt,
                        tile_img, tile_last, ntiles, round, lut, hist_bits, hist_round);
-    return hipGetLastError();
-}
-
-// --------------------------------------------------------------- k_persist
-//
-// One launch runs every image of the work list to stability.  Work item q is
-// (round r = q / ntiles, tile g = q % ntiles); items are handed out in order
-// by one atomic counter.  Item (r, g) may start once tile g and its 8
-// neighbouring tiles have completed round r - 1.  Those items were handed out
-// earlier, to blocks that are running, and the oldest item still outstanding
-// never waits, so the queue always drains; no co-residency is assumed.
-// Publishing a round: every thread fences its stores at device scope, then
-// one thread raises progress[g] with release semantics; a waiter observes it
-// with acquire semantics before the block reads the halo.
-// Convergence: per image, a ring of per-round completion counters finds the
-// last tile to finish round r; that tile finalises the image when nothing
-// was lowered during the last 4 steps of round r (or the step cap is
-// reached).  Ring entries are reused after `ring_w` rounds, more than the
-// largest round spread between two tiles of one image (a tile is at most one
-// round ahead of each neighbour).  Every wait has a time limit, and so has
-// the whole launch: on expiry the block raises sched->error and all blocks
-// leave, so every wave reaches the end of the kernel.
-
-// Reads a word other blocks update, as a read-modify-write at device scope.
-// A plain relaxed load may be served from this XCD's L2, which is not kept
-// coherent with the other XCDs' L2s, so a polling loop could keep reading a
-// stale copy; an atomic RMW is performed at the device coherence point and
-// returns the latest value without invalidating any cache.
-__device__ __forceinline__ int ld_sync(int32_t* p)
-{
-    return __hip_atomic_fetch_add(p, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <int TH, int TW, int K, int NT, bool SEED>
-__global__ __launch_bounds__(NT) void k_persist(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
-                                                const int32_t* __restrict__ tile_img,
-                                                int32_t* tile_last, int32_t* progress,
-                                                int32_t* ring, Sched* sched, int ntiles,
-                                                const TopoEntry* __restrict__ lut_g,
-                                                unsigned long long wait_ticks,
-                                                unsigned long long kernel_ticks)
-{
-    using T = Tile<TH, TW, K, NT, SEED>;
-    __shared__ uint16_t s_img[T::RH * T::RWP];
-    __shared__ uint8_t s_dirty[T::RH * T::RWP];
-    __shared__ uint32_t s_bits[T::BITS_WORDS];
-    __shared__ uint32_t s_cw[T::CW_WORDS];
-    __shared__ TopoEntry s_lut[512];
-    __shared__ int s_count, s_last;
-    __shared__ int s_item[4];  // tile, round, active, copy
-
-    const int tid = threadIdx.x;
-    for (int i = tid; i < 512; i += NT) s_lut[i] = lut_g[i];
-    const unsigned long long kernel_start = wall_clock64();
-
-    for (;;) {
-        if (tid == 0) {
-            int item_g = -1, item_r = 0, item_active = 0, item_copy = 0;
-            const unsigned long long since = wall_clock64();
-            for (;;) {
-                if (ld_sync(&sched->images_left) <= 0 || ld_sync(&sched->error)) break;
-                if (wall_clock64() - since > 2 * wait_ticks ||
-                    wall_clock64() - kernel_start > kernel_ticks) {
-                    // Items keep being skipped while an image stays unfinished:
-                    // give up rather than spin.
-                    __hip_atomic_store(&sched->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                const unsigned long long q = atomicAdd(&sched->next, 1ull);
-                const int r = (int)(q / (unsigned long long)ntiles);
-                const int g = (int)(q % (unsigned long long)ntiles);
-                const int ii = tile_img[g];
-                const ImgDev* d = imgs + ii;
-                const int64_t t0 = (int64_t)r * K;
-                if (t0 >= d->max_steps) continue;  // beyond the step cap
-                int fr = ld_sync(&cnt[ii].final_round);
-                if (fr >= 0 && r >= fr) continue;  // image already final
-                const int tiles_x = d->tiles_x, tiles_y = d->tiles_y, tile0 = d->tile0;
-                const int lt = g - tile0;
-                const int ty = lt / tiles_x, tx = lt - ty * tiles_x;
-                bool skip = false, failed = false;
-                const unsigned long long w0 = wall_clock64();
-                for (;;) {
-                    // Poll with device-scope RMW reads (no cache
-                    // invalidation); one acquire fence follows success.
-                    bool ready = ld_sync(&progress[g]) >= r;
-                    for (int dy = -1; dy <= 1 && ready; ++dy) {
-                        const int y = ty + dy;
-                        if (y < 0 || y >= tiles_y) continue;
-                        for (int dx = -1; dx <= 1 && ready; ++dx) {
-                            const int x = tx + dx;
-                            if (x < 0 || x >= tiles_x || (dx == 0 && dy == 0)) continue;
-                            ready = ld_sync(&progress[tile0 + y * tiles_x + x]) >= r;
-                        }
-                    }
-                    if (ready) {
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                        break;
-                    }
-                    fr = ld_sync(&cnt[ii].final_round);
-                    if (fr >= 0 && r >= fr) { skip = true; break; }
-                    if (ld_sync(&sched->error) || wall_clock64() - w0 > wait_ticks ||
-                        wall_clock64() - kernel_start > kernel_ticks) {
-                        failed = true;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                if (failed) {
-                    __hip_atomic_store(&sched->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-                if (skip) continue;
-                item_g = g;
-                item_r = r;
-                item_active = (r == 0 || neighbourhood_last(d, tile_last, ty, tx) >= (int)t0 - 4);
-                item_copy = tile_last[g] >= (int)t0 - K;
-                break;
-            }
-            s_item[0] = item_g;
-            s_item[1] = item_r;
-            s_item[2] = item_active;
-            s_item[3] = item_copy;
-        }
-        __syncthreads();
-        const int g = s_item[0];
-        if (g < 0) break;
-        const int r = s_item[1];
-        const int ii = tile_img[g];
-        const ImgDev* d = imgs + ii;
-        const int t0 = r * K;
-        const int nsteps = min(K, d->max_steps - t0);
-        const int lt = g - d->tile0;
-        const int ty = lt / d->tiles_x, tx = lt - ty * d->tiles_x;
-        const void* src = round_src(d, r);
-        void* dst = round_dst(d, r);
-        const int gy0 = ty * TH, gx0 = tx * TW;
-        const View v = view_of(d);
-        int last_tau = -1, count = 0;
-        if (s_item[2]) {
-            count = T::run(v, gy0, gx0, t0, nsteps, src, dst, s_img, s_dirty, s_bits, s_cw,
-                           nullptr, s_lut + d->adj * 256, &s_count, &s_last, tid, last_tau);
-        } else if (s_item[3]) {
-            T::copy_interior(v, gy0, gx0, src, dst, tid);
-        }
-        // Publishing: each wave waits until its own stores are acknowledged
-        // (a workgroup barrier alone does not wait for them), then one
-        // thread's release fence writes the L2 back for other XCDs.
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (tid == 0) {
-            if (s_item[2]) atomicAdd(&cnt[ii].tile_rounds, 1ull);
-            if (last_tau >= 0) {
-                __hip_atomic_store(&tile_last[g], t0 + last_tau, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-                atomicAdd(&cnt[ii].lowerings, (unsigned long long)count);
-                atomicMax(&cnt[ii].last_step, t0 + last_tau);
-            }
-            __hip_atomic_store(&progress[g], r + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const int slot = d->ring0 + r % d->ring_w;
-            const int done = __hip_atomic_fetch_add(&ring[slot], 1, __ATOMIC_ACQ_REL,
-                                                    __HIP_MEMORY_SCOPE_AGENT) + 1;
-            if (done == d->tiles_x * d->tiles_y) {
-                // Last tile of round r: every tile's counters of rounds <= r
-                // are in.  Later rounds cannot lower anything if this one
-                // ended quiet, so last_step decides stability exactly.
-                __hip_atomic_store(&ring[slot], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const int ls = ld_sync(&cnt[ii].last_step);
-                const int64_t steps = min((int64_t)(r + 1) * K, (int64_t)d->max_steps);
-                if ((int64_t)ls < steps - 4 || steps >= d->max_steps) {
-                    __hip_atomic_store(&cnt[ii].final_round, r + 1, __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_fetch_add(&sched->images_left, -1, __ATOMIC_ACQ_REL,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                }
-            }
-        }
-    }
-}
-
-__global__ void k_init_persist(ImgCnt* cnt, int nimg, int32_t* tile_last, int32_t* progress,
-                               int ntiles, int32_t* ring, int nring, Sched* sched)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < nimg) {
-        cnt[i].lowerings = 0ull;
-        cnt[i].tile_rounds = 0ull;
-        cnt[i].last_step = -1;
-        cnt[i].final_round = -1;
-    }
-    if (i < ntiles) {
-        tile_last[i] = -1;
-        progress[i] = 0;
-    }
-    if (i < nring) ring[i] = 0;
-    if (i == 0) {
-        sched->next = 0ull;
-        sched->images_left = nimg;
-        sched->error = 0;
-    }
-}
-
-template <int TH, int TW, int K, int NT, bool SEED>
-hipError_t launch_persist_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
-                            const int32_t* tile_img, int32_t* tile_last, int32_t* progress,
-                            int32_t* ring, Sched* sched, int ntiles, const TopoEntry* lut,
-                            int grid_blocks, unsigned long long wait_ticks,
-                            unsigned long long kernel_ticks)
-{
-    hipLaunchKernelGGL((k_persist<TH, TW, K, NT, SEED>), dim3(max(1, grid_blocks)), dim3(NT), 0, stream,
-                       imgs, cnt, tile_img, tile_last, progress, ring, sched, ntiles, lut,
-                       wait_ticks, kernel_ticks);
     return hipGetLastError();
 }
 
@@ -868,22 +873,39 @@ hipError_t launch_step(hipStream_t stream, const ImgDev* img_host, const ImgDev*
 }
 
 // Compiled tile shapes: (tile height, tile width, halo = steps per residency,
-// threads per tile, history seeding).
-#define THIN_SHAPES(X)           \
-    X(16, 16, 8, 256, false)     \
-    X(32, 32, 8, 256, false)     \
-    X(32, 32, 8, 512, false)     \
-    X(32, 32, 16, 256, false)    \
-    X(32, 32, 16, 1024, false)   \
-    X(32, 32, 16, 1024, true)    \
-    X(64, 64, 16, 1024, false)   \
-    X(64, 64, 16, 1024, true)    \
-    X(64, 64, 32, 1024, false)
+// threads per tile, residency variant).
+#define THIN_SHAPES(X)      \
+    X(16, 16, 8, 256, 0)    \
+    X(32, 32, 8, 256, 0)    \
+    X(32, 32, 8, 512, 0)    \
+    X(32, 32, 16, 256, 0)   \
+    X(32, 32, 16, 1024, 0)  \
+    X(32, 32, 16, 1024, 1)  \
+    X(64, 64, 16, 1024, 0)  \
+    X(64, 64, 16, 1024, 1)  \
+    X(64, 64, 32, 1024, 0)  \
+    X(64, 64, 8, 1024, 0)   \
+    X(64, 64, 16, 512, 0)   \
+    X(64, 64, 16, 256, 0)   \
+    X(64, 64, 32, 512, 0)   \
+    X(64, 64, 8, 512, 0)    \
+    X(48, 48, 16, 512, 0)   \
+    X(32, 32, 16, 512, 0)   \
+    X(128, 128, 16, 512, 0) \
+    X(64, 64, 16, 512, 2)   \
+    X(32, 32, 16, 512, 2)   \
+    X(16, 16, 8, 256, 2)    \
+    X(32, 32, 8, 256, 2)    \
+    X(32, 32, 16, 256, 2)   \
+    X(32, 32, 16, 1024, 2)  \
+    X(32, 32, 32, 1024, 2)  \
+    X(64, 64, 16, 1024, 2)  \
+    X(64, 64, 32, 1024, 2)
 
 bool tile_shape_supported(TileShape s)
 {
 #define X(a, b, c, n, e) \
-    if (s.th == a && s.tw == b && s.k == c && s.nt == n && s.seed == e) return true;
+    if (s.th == a && s.tw == b && s.k == c && s.nt == n && s.var == e) return true;
     THIN_SHAPES(X)
 #undef X
     return false;
@@ -895,20 +917,20 @@ TileShape complete_shape(int th, int tw, int k)
     if (th == a && tw == b && k == c) return TileShape{a, b, c, n, e};
     THIN_SHAPES(X)
 #undef X
-    return TileShape{0, 0, 0, 0, false};
+    return TileShape{0, 0, 0, 0, 0};
 }
-
-int persist_threads(TileShape s) { return s.nt; }
 
 static int lds_bytes(TileShape s)
 {
+    if (s.var == kVarRegs) return (s.th + 2 * s.k + 2) * (s.tw + 2 * s.k + 2) * 2 + 4096 + 64;
     const int region = (s.th + 2 * s.k) * (s.tw + 2 * s.k);
-    const int hist = s.seed ? (s.th * (s.tw / 32) + (s.th + 2 * s.k) * ((s.tw + 2 * s.k + 31) / 32)) * 4
-                            : 8;
+    const int hist = s.var == kVarSeeded
+                         ? (s.th * (s.tw / 32) + (s.th + 2 * s.k) * ((s.tw + 2 * s.k + 31) / 32)) * 4
+                         : 8;
     return region * 3 + hist + 4096 + 64;
 }
 
-int history_words(TileShape s) { return s.seed ? s.th * (s.tw / 32) : 1; }
+int history_words(TileShape s) { return s.var == kVarSeeded ? s.th * (s.tw / 32) : 1; }
 
 int round_blocks_per_cu(TileShape s)
 {
@@ -917,33 +939,15 @@ int round_blocks_per_cu(TileShape s)
     return max(1, min(by_lds, by_threads));
 }
 
-int persist_blocks_per_cu(TileShape s) { return round_blocks_per_cu(s); }
-
 hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                         const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
                         const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
                         int32_t* hist_round)
 {
 #define X(a, b, c, n, e)                                                                    \
-    if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.seed == e)  \
+    if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.var == e)  \
         return launch_round_t<a, b, c, n, e>(stream, imgs, cnt, tile_img, tile_last, ntiles, \
                                              round, lut, grid_blocks, hist_bits, hist_round);
-    THIN_SHAPES(X)
-#undef X
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_persist(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
-                          const int32_t* tile_img, int32_t* tile_last, int32_t* progress,
-                          int32_t* ring, Sched* sched, int ntiles, const TopoEntry* lut,
-                          int grid_blocks, unsigned long long wait_ticks,
-                          unsigned long long kernel_ticks)
-{
-#define X(a, b, c, n, e)                                                                     \
-    if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.seed == e)   \
-        return launch_persist_t<a, b, c, n, e>(stream, imgs, cnt, tile_img, tile_last,        \
-                                               progress, ring, sched, ntiles, lut, grid_blocks, \
-                                               wait_ticks, kernel_ticks);
     THIN_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
@@ -955,23 +959,13 @@ hipError_t launch_coop(hipStream_t stream, TileShape shape, const ImgDev* imgs, 
                        int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round)
 {
 #define X(a, b, c, n, e)                                                                    \
-    if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.seed == e)  \
+    if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.var == e)  \
         return launch_coop_t<a, b, c, n, e>(stream, imgs, cnt, tile_img, tile_last, ntiles,  \
                                             lut, active, rounds_out, max_rounds, num_cus,    \
                                             hist_bits, hist_round);
     THIN_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
-}
-
-hipError_t launch_init_persist(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t* tile_last,
-                               int32_t* progress, int ntiles, int32_t* ring, int nring,
-                               Sched* sched)
-{
-    const int n = max(max(nimg, ntiles), max(nring, 1));
-    hipLaunchKernelGGL(k_init_persist, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                       stream, cnt, nimg, tile_last, progress, ntiles, ring, nring, sched);
-    return hipGetLastError();
 }
 
 }  // namespace thin

@@ -114,14 +114,12 @@ struct thin_ctx {
     hipStream_t stream = nullptr;
     uint64_t max_device_bytes = 0;
     uint64_t max_passes = 0;
-    TileShape forced{0, 0, 0, 0, false};
+    TileShape forced{0, 0, 0, 0, 0};
     int num_cus = 256;
 
     TopoEntry* d_lut = nullptr;
     uint64_t allocated = 0;        // bytes of scratch currently held
-    DevBuf twin, imgs, cnt, tile_img, tile_last, progress, ring, sched, hist_bits, hist_round;
-    unsigned long long wait_ticks = 0;     // dependency-wait limit of the persistent kernel
-    unsigned long long kernel_ticks = 0;   // whole-launch limit of the persistent kernel
+    DevBuf twin, imgs, cnt, tile_img, tile_last, small, hist_bits, hist_round;
     ImgCnt* h_snap[2] = {nullptr, nullptr};   // pinned snapshots of the counters
     size_t h_snap_cap = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -275,8 +273,13 @@ int steps_cap(const thin_ctx* ctx)
 TileShape choose_shape(const thin_ctx* ctx, int64_t total_pixels)
 {
     if (ctx->forced.th) return ctx->forced;
-    if (total_pixels <= (int64_t)4 << 20) return TileShape{32, 32, 16, 1024, false};
-    return TileShape{64, 64, 16, 1024, false};
+    // Small work lists are bound by the latency of each round: small tiles
+    // with one cell per thread and register windows.  Large ones are bound by
+    // throughput: big tiles (less halo work) and 512-thread blocks, several
+    // per CU, so one block's staging overlaps another's steps.
+    if (total_pixels <= (int64_t)1 << 20) return TileShape{32, 32, 16, 1024, thin::kVarRegs};
+    if (total_pixels <= (int64_t)32 << 20) return TileShape{64, 64, 16, 512, thin::kVarFlags};
+    return TileShape{128, 128, 16, 512, thin::kVarFlags};
 }
 
 void fill_stats(thin_stats* st, const ImgCnt& c, int steps_done, int max_steps, bool trivial)
@@ -507,7 +510,7 @@ int run_coop(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
     if ((rc = ensure(ctx, ctx->cnt, sizeof(ImgCnt) * nimg))) return rc;
     if ((rc = ensure(ctx, ctx->tile_img, sizeof(int32_t) * ntiles))) return rc;
     if ((rc = ensure(ctx, ctx->tile_last, sizeof(int32_t) * 2 * (size_t)ntiles))) return rc;
-    if ((rc = ensure(ctx, ctx->sched, 64))) return rc;
+    if ((rc = ensure(ctx, ctx->small, 64))) return rc;
     if ((rc = ensure(ctx, ctx->hist_bits,
                      sizeof(uint32_t) * 2 * (size_t)ntiles * thin::history_words(shape))))
         return rc;
@@ -518,7 +521,7 @@ int run_coop(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
     ImgCnt* d_cnt = static_cast<ImgCnt*>(ctx->cnt.ptr);
     int32_t* d_tile_img = static_cast<int32_t*>(ctx->tile_img.ptr);
     int32_t* d_tile_last = static_cast<int32_t*>(ctx->tile_last.ptr);
-    int32_t* d_small = static_cast<int32_t*>(ctx->sched.ptr);  // [0..2] active, [3] rounds
+    int32_t* d_small = static_cast<int32_t*>(ctx->small.ptr);  // [0..2] active, [3] rounds
     HIP_TRY(ctx, hipMemcpyAsync(d_imgs, plan.imgs.data(), sizeof(ImgDev) * nimg,
                                 hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(d_tile_img, plan.tile_img.data(), sizeof(int32_t) * ntiles,
@@ -570,135 +573,6 @@ int run_coop(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
         fill_stats(&st, fin[i], steps, d.max_steps, false);
         if (!st.converged) limited = true;
         if (stats) stats[plan.src_index[i]] = st;
-    }
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    return limited ? fail(ctx, THIN_ELIMIT, "max_passes reached before stability") : THIN_OK;
-}
-
-// ----------------------------------------------------------- persistent engine
-
-int run_persist(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
-                thin_stats* stats)
-{
-    int64_t total_px = 0;
-    for (int i : work) total_px += ims[i].h * ims[i].w;
-    const TileShape shape = choose_shape(ctx, total_px);
-    if (!thin::tile_shape_supported(shape))
-        return fail(ctx, THIN_EINVAL, "unsupported tile shape %dx%d k=%d", shape.th, shape.tw, shape.k);
-    const int K = shape.k;
-    const int max_steps = steps_cap(ctx);
-
-    std::vector<ImgDev> imgs;
-    std::vector<int32_t> tile_img;
-    size_t twin_bytes = 0;
-    std::vector<size_t> twin_off;
-    for (int i : work) {
-        const thin_image& im = ims[i];
-        const size_t bpp = im.dtype == THIN_U8 ? 1 : 2;
-        twin_off.push_back(twin_bytes);
-        twin_bytes += ((size_t)im.h * (size_t)pitch_of(im) * bpp + 255) & ~size_t(255);
-    }
-    int rc = ensure(ctx, ctx->twin, std::max<size_t>(twin_bytes, 256));
-    if (rc) return rc;
-    int nring = 0;
-    for (size_t n = 0; n < work.size(); ++n) {
-        const thin_image& im = ims[work[n]];
-        ImgDev d{};
-        d.buf[0] = im.image;
-        d.buf[1] = static_cast<char*>(ctx->twin.ptr) + twin_off[n];
-        d.pitch = pitch_of(im);
-        d.h = (int32_t)im.h;
-        d.w = (int32_t)im.w;
-        d.dtype = im.dtype;
-        d.lambda = im.lambda;
-        d.adj = im.adjacency;
-        d.tiles_y = (int32_t)((im.h + shape.th - 1) / shape.th);
-        d.tiles_x = (int32_t)((im.w + shape.tw - 1) / shape.tw);
-        d.tile0 = (int32_t)tile_img.size();
-        d.round0 = 0;
-        d.max_steps = max_steps;
-        d.ring_w = std::max(d.tiles_x, d.tiles_y) + 3;
-        d.slot = (int32_t)imgs.size();
-        d.state0 = d.tile0;
-        d.ring0 = nring;
-        nring += d.ring_w;
-        const int64_t nt = (int64_t)d.tiles_x * d.tiles_y;
-        if ((int64_t)tile_img.size() + nt > INT_MAX / 2)
-            return fail(ctx, THIN_EINVAL, "too many tiles in one call");
-        for (int64_t t = 0; t < nt; ++t) tile_img.push_back((int32_t)imgs.size());
-        imgs.push_back(d);
-    }
-    const int nimg = (int)imgs.size();
-    const int ntiles = (int)tile_img.size();
-    if ((rc = ensure(ctx, ctx->imgs, sizeof(ImgDev) * nimg))) return rc;
-    if ((rc = ensure(ctx, ctx->cnt, sizeof(ImgCnt) * nimg))) return rc;
-    if ((rc = ensure(ctx, ctx->tile_img, sizeof(int32_t) * ntiles))) return rc;
-    if ((rc = ensure(ctx, ctx->tile_last, sizeof(int32_t) * ntiles))) return rc;
-    if ((rc = ensure(ctx, ctx->progress, sizeof(int32_t) * ntiles))) return rc;
-    if ((rc = ensure(ctx, ctx->ring, sizeof(int32_t) * nring))) return rc;
-    if ((rc = ensure(ctx, ctx->sched, sizeof(thin::Sched)))) return rc;
-    if ((rc = ensure_snap(ctx, nimg))) return rc;
-
-    ImgDev* d_imgs = static_cast<ImgDev*>(ctx->imgs.ptr);
-    ImgCnt* d_cnt = static_cast<ImgCnt*>(ctx->cnt.ptr);
-    thin::Sched* d_sched = static_cast<thin::Sched*>(ctx->sched.ptr);
-    HIP_TRY(ctx, hipMemcpyAsync(d_imgs, imgs.data(), sizeof(ImgDev) * nimg, hipMemcpyHostToDevice,
-                                ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->tile_img.ptr, tile_img.data(), sizeof(int32_t) * ntiles,
-                                hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, thin::launch_init_persist(ctx->stream, d_cnt, nimg,
-                                           static_cast<int32_t*>(ctx->tile_last.ptr),
-                                           static_cast<int32_t*>(ctx->progress.ptr), ntiles,
-                                           static_cast<int32_t*>(ctx->ring.ptr), nring, d_sched));
-    const int capacity = ctx->num_cus * thin::persist_blocks_per_cu(shape);
-    const int grid = std::max(1, std::min(capacity, 2 * ntiles));
-    size_t ev_used = 0;
-    if (ctx->profile) {
-        while (ctx->prof_ev.size() < 2) {
-            hipEvent_t e;
-            HIP_TRY(ctx, hipEventCreate(&e));
-            ctx->prof_ev.push_back(e);
-        }
-        HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[0], ctx->stream));
-    }
-    HIP_TRY(ctx, thin::launch_persist(ctx->stream, shape, d_imgs, d_cnt,
-                                      static_cast<const int32_t*>(ctx->tile_img.ptr),
-                                      static_cast<int32_t*>(ctx->tile_last.ptr),
-                                      static_cast<int32_t*>(ctx->progress.ptr),
-                                      static_cast<int32_t*>(ctx->ring.ptr), d_sched, ntiles,
-                                      ctx->d_lut, grid, ctx->wait_ticks, ctx->kernel_ticks));
-    if (ctx->profile) {
-        HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[1], ctx->stream));
-        ev_used = 2;
-    }
-    thin::Sched h_sched{};
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_snap[0], d_cnt, sizeof(ImgCnt) * nimg,
-                                hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    HIP_TRY(ctx, hipMemcpy(&h_sched, d_sched, sizeof h_sched, hipMemcpyDeviceToHost));
-    const ImgCnt* fin = ctx->h_snap[0];
-    if (h_sched.error)
-        return fail(ctx, THIN_EDEVICE, "persistent kernel: a wait or the launch exceeded its time limit");
-    if (ctx->profile) {
-        if ((rc = collect_profile(ctx, ev_used))) return rc;
-        for (int i = 0; i < nimg; ++i) ctx->prof_tile_rounds += fin[i].tile_rounds;
-    }
-    bool limited = false;
-    for (int i = 0; i < nimg; ++i) {
-        const ImgDev& d = imgs[i];
-        if (fin[i].final_round < 0)
-            return fail(ctx, THIN_EDEVICE, "persistent kernel ended with image %d unfinished", i);
-        if (fin[i].final_round & 1) {
-            const size_t bpp = d.dtype == THIN_U8 ? 1 : 2;
-            HIP_TRY(ctx, hipMemcpy2DAsync(d.buf[0], d.pitch * bpp, d.buf[1], d.pitch * bpp,
-                                          (size_t)d.w * bpp, (size_t)d.h,
-                                          hipMemcpyDeviceToDevice, ctx->stream));
-        }
-        const int steps = (int)std::min<int64_t>((int64_t)fin[i].final_round * K, d.max_steps);
-        thin_stats st;
-        fill_stats(&st, fin[i], steps, d.max_steps, false);
-        if (!st.converged) limited = true;
-        if (stats) stats[work[i]] = st;
     }
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return limited ? fail(ctx, THIN_ELIMIT, "max_passes reached before stability") : THIN_OK;
@@ -767,12 +641,8 @@ int run_images(thin_ctx* ctx, const thin_image* ims, int n, thin_stats* stats)
     if (work.empty()) return THIN_OK;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if (ctx->engine == THIN_ENGINE_STEP) return run_step_engine(ctx, ims, work, stats);
-    if (ctx->engine == THIN_ENGINE_PERSIST) {
-        // Switched off: a launch of this engine once ran past its time guards
-        // without finishing, and the cause is not established.
-        (void)run_persist;
-        return fail(ctx, THIN_EINVAL, "the persistent engine is disabled");
-    }
+    if (ctx->engine == THIN_ENGINE_PERSIST)
+        return fail(ctx, THIN_EINVAL, "the persistent engine is not available");
     if (ctx->engine == THIN_ENGINE_COOP) return run_coop(ctx, ims, work, stats);
     return run_tiled(ctx, ims, work, stats);
 }
@@ -791,19 +661,17 @@ int thin_create(thin_ctx** out, const thin_config* cfg)
     if (cfg) c = *cfg;
     if (c.engine < 0 || c.engine > THIN_ENGINE_COOP) return THIN_EINVAL;
     if ((c.tile != 0) != (c.steps_per_round != 0)) return THIN_EINVAL;
-    TileShape forced{0, 0, 0, 0, false};
+    TileShape forced{0, 0, 0, 0, 0};
     if (c.tile) {
         forced = thin::complete_shape(c.tile, c.tile, c.steps_per_round);
         if (!forced.nt) return THIN_EINVAL;
     }
-    // THIN_TILE_SHAPE="th,tw,k,threads,seed" selects any compiled shape (tuning).
+    // THIN_TILE_SHAPE="th,tw,k,threads,variant" selects any compiled shape (tuning).
     if (const char* env = getenv("THIN_TILE_SHAPE")) {
-        TileShape e{0, 0, 0, 0, false};
-        int seed = 0;
-        if (sscanf(env, "%d,%d,%d,%d,%d", &e.th, &e.tw, &e.k, &e.nt, &seed) == 5) {
-            e.seed = seed != 0;
-            if (thin::tile_shape_supported(e)) forced = e;
-        }
+        TileShape e{0, 0, 0, 0, 0};
+        if (sscanf(env, "%d,%d,%d,%d,%d", &e.th, &e.tw, &e.k, &e.nt, &e.var) == 5 &&
+            thin::tile_shape_supported(e))
+            forced = e;
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
@@ -827,16 +695,6 @@ int thin_create(thin_ctx** out, const thin_config* cfg)
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device) == hipSuccess &&
             cus > 0)
             ctx->num_cus = cus;
-        // Dependency waits of the persistent kernel give up after 5 s of
-        // device wall-clock time (a healthy wait lasts microseconds).
-        int rate_khz = 0;
-        if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c.device) != hipSuccess ||
-            rate_khz <= 0)
-            rate_khz = 100000;
-        ctx->wait_ticks = (unsigned long long)rate_khz * 1000ull * 5ull;
-        // A whole persistent launch gives up after 60 s (the largest images
-        // here take well under a second).
-        ctx->kernel_ticks = (unsigned long long)rate_khz * 1000ull * 60ull;
         TopoEntry table[512];
         thin::build_topology_table(0, table);
         thin::build_topology_table(1, table + 256);
@@ -886,7 +744,7 @@ int thin_destroy(thin_ctx* ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&ctx->twin,       &ctx->imgs,        &ctx->cnt,        &ctx->tile_img,
-                      &ctx->tile_last,  &ctx->progress,    &ctx->ring,       &ctx->sched,
+                      &ctx->tile_last,  &ctx->small,
                       &ctx->hist_bits,  &ctx->hist_round,  &ctx->serve_twin, &ctx->serve_state,
                       &ctx->serve_cnt,  &ctx->serve_imgs,  &ctx->serve_tile_img};
     for (DevBuf* b : bufs)
@@ -963,8 +821,8 @@ int thin_serve_admit(thin_ctx* ctx, const thin_image* img, uint64_t tag)
     }
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if (!ctx->serve_ready) {
-        TileShape shape = choose_shape(ctx, 0);
-        if (shape.seed) shape = TileShape{shape.th, shape.tw, shape.k, shape.nt, false};
+        TileShape shape = choose_shape(ctx, (int64_t)16 << 20);
+        if (shape.var == thin::kVarSeeded) shape.var = thin::kVarFlags;
         if (!thin::tile_shape_supported(shape))
             return fail(ctx, THIN_EINVAL, "no compiled serving shape %dx%d k=%d", shape.th,
                         shape.tw, shape.k);

@@ -102,10 +102,17 @@ def test_fuzz(case):
     assert_same(F, lam, adj, got, st)
 
 
-# Every compiled (tile height, width, halo, threads, history seeding) shape.
+# Every compiled (tile height, width, halo, threads, residency variant) shape:
+# variant 0 keeps per-pixel flags in LDS, 1 seeds them from the previous
+# round, 2 keeps 4x4 windows in registers.
 ALL_SHAPES = ["16,16,8,256,0", "32,32,8,256,0", "32,32,8,512,0", "32,32,16,256,0",
-              "32,32,16,1024,0", "32,32,16,1024,1", "64,64,16,1024,0", "64,64,16,1024,1",
-              "64,64,32,1024,0"]
+              "32,32,16,512,0", "32,32,16,1024,0", "32,32,16,1024,1", "48,48,16,512,0",
+              "64,64,8,512,0", "64,64,8,1024,0", "64,64,16,256,0", "64,64,16,512,0",
+              "64,64,16,1024,0", "64,64,16,1024,1", "64,64,32,512,0", "64,64,32,1024,0",
+              "128,128,16,512,0",
+              "16,16,8,256,2", "32,32,8,256,2", "32,32,16,256,2", "32,32,16,512,2",
+              "32,32,16,1024,2", "32,32,32,1024,2", "64,64,16,512,2", "64,64,16,1024,2",
+              "64,64,32,1024,2"]
 
 
 @pytest.mark.parametrize("shape", ALL_SHAPES)
@@ -202,7 +209,7 @@ def test_degenerate_sizes(shape):
     assert st.passes == ref.passes and st.lowerings == ref.lowerings
 
 
-@pytest.mark.skip(reason="persistent engine disabled: one launch ran past its time guards "
+@pytest.mark.skip(reason="persistent engine removed: one launch ran past its time guards "
                          "without finishing and the cause is not established")
 def test_persistent_engine_blobs_128():
     job = synth.blobs_128()
