@@ -34,6 +34,21 @@ struct ImgCnt {
     int32_t pad;
 };
 
+// Tiles a round launch visits.  With list == nullptr every tile is visited.
+// Otherwise launch round R visits list[(R & 1) * cap + i] for i < count[R % 3]
+// (every tile when full != 0), and a tile appends the tiles that must be
+// visited in round R + 1 (its 3x3 tile block when it lowered something during
+// its last 4 steps, itself when it lowered anything) to the other half,
+// deduplicated by listed[g] = last round g was queued for.  count[(R + 2) % 3]
+// is cleared during round R, before round R + 1 appends to it.
+struct WorkList {
+    int32_t* list;
+    int32_t* count;
+    int32_t* listed;
+    int32_t cap;
+    int32_t full;
+};
+
 // Connectivity table entry for an upper-neighbour mask (see thin_topology_table).
 //   x: bit 0 destructible, bits 4..6 T--, bits 8..10 T+
 //   y: byte c = ring mask of the c-th counted lower component
@@ -46,28 +61,40 @@ struct TopoEntry {
 void build_topology_table(int adjacency, TopoEntry out[256]);
 
 // Residency variants.  kVarFlags keeps the tile in LDS with a re-examination
-// flag per pixel; kVarSeeded also starts those flags from the previous
-// round's change bitmaps; kVarRegs keeps each thread's 4x4 windows in
-// registers and tracks re-examination per window.
-constexpr int kVarFlags = 0, kVarSeeded = 1, kVarRegs = 2;
+// flag byte per pixel, every thread checking fixed cells each step;
+// kVarSeeded also starts those flags from the previous round's change
+// bitmaps; kVarRegs keeps each thread's 4x4 windows in registers;
+// kVarBits keeps the flags as one bit per candidate and class and gathers
+// each step's flagged candidates into a dense list; kVarBitsSeeded adds the
+// previous round's change bitmaps to kVarBits.
+constexpr int kVarFlags = 0, kVarSeeded = 1, kVarRegs = 2, kVarBits = 3, kVarBitsSeeded = 4;
+
+// Variants that read and write per-tile change bitmaps between rounds.
+constexpr bool var_seeded(int v) { return v == kVarSeeded || v == kVarBitsSeeded; }
+// The same variant without history (for callers that keep none).
+constexpr int var_unseeded(int v)
+{
+    return v == kVarSeeded ? kVarFlags : (v == kVarBitsSeeded ? kVarBits : v);
+}
 
 // Tiled engine geometry chosen at run time among the compiled variants.
 struct TileShape {
     int th, tw, k;   // tile height, width, halo = parity steps per residency
     int nt;          // threads per tile
-    int var;         // residency variant: kVarFlags, kVarSeeded or kVarRegs
+    int var;         // residency variant (kVar*)
 };
 
 // The compiled shape with this tile and halo (nt = 0 when there is none).
 TileShape complete_shape(int th, int tw, int k);
 
 // Kernel launchers (thin_kernels.hip).  All enqueue on `stream`.
+// Clears counters and tile state; with wl.list, listed[] = -1 and counts 0.
 hipError_t launch_init_state(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t* tile_last,
-                             int ntiles, int32_t* hist_round);
+                             int ntiles, int32_t* hist_round, WorkList wl);
 hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                         const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
                         const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
-                        int32_t* hist_round);
+                        int32_t* hist_round, WorkList wl);
 // Words of one tile's change bitmap (two copies of ntiles bitmaps are needed).
 int history_words(TileShape s);
 hipError_t launch_step(hipStream_t stream, const ImgDev* img_host, const ImgDev* img_dev,

@@ -100,9 +100,13 @@ __device__ __forceinline__ void store_px(void* base, int dtype, int64_t idx, uin
 // ------------------------------------------------------------------ k_init
 
 __global__ void k_init_state(ImgCnt* cnt, int nimg, int32_t* tile_last, int ntiles,
-                             int32_t* hist_round)
+                             int32_t* hist_round, WorkList wl)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (wl.list != nullptr) {
+        if (i < ntiles) wl.listed[i] = -1;
+        if (i < 3) wl.count[i] = 0;
+    }
     if (hist_round && i < 2 * ntiles) hist_round[i] = -1;
     if (i < nimg) {
         cnt[i].lowerings = 0ull;
@@ -179,6 +183,123 @@ __device__ __forceinline__ const void* round_src(const ImgDev* d, int r)
 __device__ __forceinline__ void* round_dst(const ImgDev* d, int r)
 {
     return d->buf[(r + 1) & 1];
+}
+
+// ------------------------------------------------------- wide tile transfers
+//
+// Groups of 4 pixels move as one dword (u8) or two (u16) when both
+// ping-pong buffers and the pitch are aligned to a group (the twin is
+// 256-byte aligned, so the caller's buffer and pitch decide).  Region and
+// interior columns start at multiples of 4, so a group lies wholly left of
+// the image or starts inside it; only the last group of a row can be cut by
+// the right border, and it moves pixel by pixel.
+
+__device__ __forceinline__ bool wide_ok(const View& d, const void* a, const void* b)
+{
+    const uintptr_t al = d.dtype == 1 ? 4u : 8u;
+    return (d.pitch & 3) == 0 && ((uintptr_t)a % al) == 0 && ((uintptr_t)b % al) == 0;
+}
+
+// 4 pixels as two u16 pairs (pixel 0 in the low half of .x).
+__device__ __forceinline__ uint2 load4(const uint8_t* p)
+{
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(p);
+    return make_uint2((w & 0xFFu) | ((w << 8) & 0xFF0000u), ((w >> 16) & 0xFFu) | ((w >> 8) & 0xFF0000u));
+}
+__device__ __forceinline__ uint2 load4(const uint16_t* p) { return *reinterpret_cast<const uint2*>(p); }
+
+__device__ __forceinline__ void store4(uint8_t* p, uint2 v)
+{
+    *reinterpret_cast<uint32_t*>(p) = (v.x & 0xFFu) | ((v.x >> 8) & 0xFF00u) | ((v.y & 0xFFu) << 16) |
+                                      ((v.y << 8) & 0xFF000000u);
+}
+__device__ __forceinline__ void store4(uint16_t* p, uint2 v) { *reinterpret_cast<uint2*>(p) = v; }
+
+template <typename P>
+__device__ __forceinline__ uint2 load_partial(const P* p, int n)
+{
+    uint32_t q[4] = {0u, 0u, 0u, 0u};
+    for (int i = 0; i < n; ++i) q[i] = p[i];
+    return make_uint2(q[0] | (q[1] << 16), q[2] | (q[3] << 16));
+}
+
+template <typename P>
+__device__ __forceinline__ void store_partial(P* p, uint2 v, int n)
+{
+    const uint32_t q[4] = {v.x & 0xFFFFu, v.x >> 16, v.y & 0xFFFFu, v.y >> 16};
+    for (int i = 0; i < n; ++i) p[i] = (P)q[i];
+}
+
+// Region rows [0, RH) x columns [0, RW) of src, origin (ry0, rx0), into
+// s_img (u16, row pitch RWP); zeros outside the image.
+template <typename P, int RH, int RW, int RWP, int NT>
+__device__ __forceinline__ void stage_wide(const View& d, const P* src, int ry0, int rx0,
+                                           uint16_t* s_img, int tid)
+{
+    static_assert(RW % 4 == 0 && RWP % 4 == 0, "groups of 4 pixels");
+    constexpr int GW = RW / 4, NG = RH * GW;
+    constexpr int ITER = (NG + NT - 1) / NT;
+    constexpr int CH = ITER < STAGE_CHUNK ? ITER : STAGE_CHUNK;
+#pragma unroll 1
+    for (int k0 = 0; k0 < ITER; k0 += CH) {
+        uint2 v[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int g = tid + (k0 + c) * NT;
+            const int y = g / GW, x = 4 * (g - (g / GW) * GW);
+            const int gi = ry0 + y, gj = rx0 + x;
+            v[c] = make_uint2(0u, 0u);
+            if (g < NG && gi >= 0 && gi < d.h && gj >= 0 && gj < d.w) {
+                const P* row = src + (int64_t)gi * d.pitch + gj;
+                v[c] = gj + 4 <= d.w ? load4(row) : load_partial(row, d.w - gj);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int g = tid + (k0 + c) * NT;
+            if (g < NG) {
+                const int y = g / GW, x = 4 * (g - (g / GW) * GW);
+                *reinterpret_cast<uint2*>(s_img + y * RWP + x) = v[c];
+            }
+        }
+    }
+}
+
+// Interior rows [0, TH) x columns [0, TW) of s_img (origin (OY, OX) in it)
+// to dst at (gy0, gx0), clipped to the image.
+template <typename P, int TH, int TW, int RWP, int OY, int OX, int NT>
+__device__ __forceinline__ void store_wide(const View& d, P* dst, int gy0, int gx0,
+                                           const uint16_t* s_img, int tid)
+{
+    static_assert(TW % 4 == 0 && OX % 4 == 0 && RWP % 4 == 0, "groups of 4 pixels");
+    constexpr int GW = TW / 4;
+    const int ih = min(TH, d.h - gy0), iw = min(TW, d.w - gx0);
+    for (int g = tid; g < TH * GW; g += NT) {
+        const int y = g / GW, x = 4 * (g - (g / GW) * GW);
+        if (y < ih && x < iw) {
+            const uint2 v = *reinterpret_cast<const uint2*>(s_img + (OY + y) * RWP + OX + x);
+            P* q = dst + (int64_t)(gy0 + y) * d.pitch + gx0 + x;
+            if (x + 4 <= iw) store4(q, v);
+            else store_partial(q, v, iw - x);
+        }
+    }
+}
+
+// Interior copy src -> dst in groups of 4.
+template <typename P, int TH, int TW, int NT>
+__device__ __forceinline__ void copy_wide(const View& d, const P* src, P* dst, int gy0, int gx0,
+                                          int tid)
+{
+    constexpr int GW = TW / 4;
+    const int ih = min(TH, d.h - gy0), iw = min(TW, d.w - gx0);
+    for (int g = tid; g < TH * GW; g += NT) {
+        const int y = g / GW, x = 4 * (g - (g / GW) * GW);
+        if (y < ih && x < iw) {
+            const int64_t o = (int64_t)(gy0 + y) * d.pitch + gx0 + x;
+            if (x + 4 <= iw) store4(dst + o, load4(src + o));
+            else store_partial(dst + o, load_partial(src + o, iw - x), iw - x);
+        }
+    }
 }
 
 // History handed from one round to the next: for every tile processed in a
@@ -640,21 +761,321 @@ struct RTile {
     }
 };
 
+// Residency with bit flags and dense work lists.  The re-examination flags
+// are one bit per lattice cell and parity class (4 bitmaps of LAT_H rows of
+// LWW words).  Each step takes the flagged candidates of its class inside
+// the exact region (one bitmap word per thread), clears those bits, and
+// writes the candidates into a list in LDS at offsets from a block-wide
+// prefix sum; the block then examines the list densely, so clean candidates
+// cost nothing beyond their share of one word.  A lowered pixel sets the
+// bits of its whole 3x3 (section 2.2 re-examination rule, as in the other
+// variants).  With SEED, the initial flags of round r > 0 come from the
+// change bitmaps of round r - 1 (the pixels that tiles lowered during their
+// last 4 steps), dilated by the 3x3, instead of all ones: a candidate whose
+// 3x3 saw none of those changes was examined 4 steps earlier at the same
+// values.
+template <int TH, int TW, int K, int NT, bool SEED>
+struct BTile {
+    static constexpr int RH = TH + 2 * K;
+    static constexpr int RW = TW + 2 * K;
+    static constexpr int RWP = RW;
+    static constexpr int IMG_ELEMS = RH * RWP;
+    static constexpr int LAT_H = RH / 2, LAT_W = RW / 2;
+    static constexpr int NCELL = LAT_H * LAT_W;
+    static constexpr int LWW = (LAT_W + 31) / 32;     // bitmap words per lattice row
+    static constexpr int CLASS_WORDS = LAT_H * LWW;   // bitmap words per class
+    static constexpr int NWAVE = NT / 64;
+    static constexpr int LIST_ELEMS = (NCELL + 1) & ~1;
+    // LDS bytes behind the flag pointer: 4 bitmaps, the list, wave totals
+    static constexpr int DIRTY_ELEMS = 16 * CLASS_WORDS + 2 * LIST_ELEMS + 4 * NWAVE;
+    static constexpr int WPR = TW >= 32 ? TW / 32 : 1;
+    static constexpr int RWW = (RW + 31) / 32;
+    static constexpr int BITS_WORDS = SEED ? TH * WPR : 1;
+    static constexpr int CW_WORDS = SEED ? RH * RWW : 1;
+    static_assert(K % 4 == 0, "a residency must start at parity class 0");
+    static_assert(K <= TH && K <= TW, "halo must not exceed the tile side");
+    static_assert(TH % 4 == 0 && TW % 4 == 0, "tile sides must be multiples of 4");
+    static_assert(NT % 64 == 0 && CLASS_WORDS <= NT, "one bitmap word per thread");
+    static_assert(NCELL < 65536, "list entries are 16-bit");
+    static_assert(!SEED || TW % 32 == 0, "history bitmaps need a tile width multiple of 32");
+    static_assert(!SEED || 2 * K <= TH, "history seeding needs the region inside the 3x3 tile block");
+
+    static __device__ void copy_interior(const View d, int gy0, int gx0, const void* src,
+                                         void* dst, int tid)
+    {
+        if (!wide_ok(d, src, dst))
+            Tile<TH, TW, K, NT, false>::copy_interior(d, gy0, gx0, src, dst, tid);
+        else if (d.dtype == 1)
+            copy_wide<uint8_t, TH, TW, NT>(d, static_cast<const uint8_t*>(src),
+                                           static_cast<uint8_t*>(dst), gy0, gx0, tid);
+        else
+            copy_wide<uint16_t, TH, TW, NT>(d, static_cast<const uint16_t*>(src),
+                                            static_cast<uint16_t*>(dst), gy0, gx0, tid);
+    }
+
+    // Bits of lattice word j that exist (cells b < LAT_W).
+    static __device__ __forceinline__ uint32_t valid_bits(int j)
+    {
+        constexpr int tail = LAT_W - 32 * (LWW - 1);
+        return (j < LWW - 1 || tail == 32) ? ~0u : ((1u << tail) - 1u);
+    }
+
+    // Even bits of x packed into the low 16 bits.
+    static __device__ __forceinline__ uint32_t even_bits(uint32_t x)
+    {
+        x &= 0x55555555u;
+        x = (x | (x >> 1)) & 0x33333333u;
+        x = (x | (x >> 2)) & 0x0F0F0F0Fu;
+        x = (x | (x >> 4)) & 0x00FF00FFu;
+        x = (x | (x >> 8)) & 0x0000FFFFu;
+        return x;
+    }
+
+    // Same contract as Tile::run.
+    static __device__ __forceinline__ int run(const View d, int gy0, int gx0, int t0, int nsteps,
+                                              const void* src, void* dst, uint16_t* s_img,
+                                              uint8_t* s_flags, uint32_t* s_bits, uint32_t* s_cw,
+                                              const Seed* sd, const TopoEntry* lut, int* s_count,
+                                              int* s_last, int tid, int& last_tau)
+    {
+        (void)t0;  // a multiple of 4: step tau has class tau mod 4
+        uint32_t* s_db = reinterpret_cast<uint32_t*>(s_flags);           // [4][LAT_H][LWW]
+        uint16_t* s_list = reinterpret_cast<uint16_t*>(s_db + 4 * CLASS_WORDS);
+        int* s_wsum = reinterpret_cast<int*>(s_list + LIST_ELEMS);
+        const int ry0 = gy0 - K, rx0 = gx0 - K;
+        const bool seeded = SEED && sd != nullptr && sd->r > 0;
+        if (tid == 0) {
+            *s_count = 0;
+            *s_last = -1;
+        }
+        if constexpr (SEED)
+            for (int i = tid; i < TH * WPR; i += NT) s_bits[i] = 0u;
+        const bool wide = wide_ok(d, src, dst);
+        if (wide && d.dtype == 1) {
+            stage_wide<uint8_t, RH, RW, RWP, NT>(d, static_cast<const uint8_t*>(src), ry0, rx0,
+                                                 s_img, tid);
+        } else if (wide) {
+            stage_wide<uint16_t, RH, RW, RWP, NT>(d, static_cast<const uint16_t*>(src), ry0, rx0,
+                                                  s_img, tid);
+        } else {
+            constexpr int ITER = (RH * RW + NT - 1) / NT;
+            constexpr int CH = ITER < STAGE_CHUNK ? ITER : STAGE_CHUNK;
+#pragma unroll 1
+            for (int k0 = 0; k0 < ITER; k0 += CH) {
+                uint32_t vals[CH];
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int idx = tid + (k0 + c) * NT;
+                    const int y = idx / RW, x = idx - y * RW;
+                    const int gi = ry0 + y, gj = rx0 + x;
+                    vals[c] = 0;
+                    if (idx < RH * RW && gi >= 0 && gi < d.h && gj >= 0 && gj < d.w)
+                        vals[c] = load_px(src, d.dtype, (int64_t)gi * d.pitch + gj);
+                }
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    const int idx = tid + (k0 + c) * NT;
+                    const int y = idx / RW, x = idx - y * RW;
+                    if (idx < RH * RW) s_img[y * RWP + x] = (uint16_t)vals[c];
+                }
+            }
+        }
+        if (!seeded) {
+            for (int i = tid; i < 4 * CLASS_WORDS; i += NT) s_db[i] = valid_bits(i % LWW);
+        } else if constexpr (SEED) {
+            // Changed map of the region in 32-pixel words, as in Tile.
+            for (int it = tid; it < RH * RWW; it += NT) {
+                const int y = it / RWW, j = it - y * RWW;
+                const int gi = ry0 + y;
+                uint32_t word = 0u;
+                if (gi >= 0 && gi < d.h) {
+                    const int c0 = rx0 + 32 * j;
+                    const int a = (c0 >= 0) ? (c0 >> 5) : -((31 - c0) >> 5);
+                    const int sh = c0 - 32 * a;
+                    const uint32_t lo = history_word_t<TH, TW>(sd, gi, a);
+                    const uint32_t hi = history_word_t<TH, TW>(sd, gi, a + 1);
+                    word = sh ? ((lo >> sh) | (hi << (32 - sh))) : lo;
+                }
+                s_cw[it] = word;
+            }
+        }
+        __syncthreads();
+        if constexpr (SEED) if (seeded) {
+            // Flag word j of class (si, sj) at lattice row a covers region
+            // row 2a + si, columns 64j + sj + 2t (t < 32): the 3x3-dilated
+            // changed map there, odd or even columns packed.
+            for (int i = tid; i < 4 * CLASS_WORDS; i += NT) {
+                const int c = i / CLASS_WORDS, rem = i - c * CLASS_WORDS;
+                const int a = rem / LWW, j = rem - a * LWW;
+                const int y = 2 * a + (c >> 1), sj = c & 1;
+                uint32_t half[2];
+#pragma unroll
+                for (int hw = 0; hw < 2; ++hw) {
+                    const int w = 2 * j + hw;
+                    uint32_t m = 0u;
+                    if (w < RWW) {
+                        for (int dy = -1; dy <= 1; ++dy) {
+                            const int yy = y + dy;
+                            if (yy < 0 || yy >= RH) continue;
+                            const uint32_t cc = s_cw[yy * RWW + w];
+                            const uint32_t l = w > 0 ? s_cw[yy * RWW + w - 1] : 0u;
+                            const uint32_t r = w + 1 < RWW ? s_cw[yy * RWW + w + 1] : 0u;
+                            m |= cc | (cc << 1) | (cc >> 1) | (l >> 31) | (r << 31);
+                        }
+                    }
+                    half[hw] = even_bits(m >> sj);
+                }
+                s_db[i] = (half[0] | (half[1] << 16)) & valid_bits(j);
+            }
+            __syncthreads();
+        }
+
+        const uint32_t lambda = d.lambda;
+        const int wave = tid >> 6, lane = tid & 63;
+        const int wa = tid / LWW, wj = tid - (tid / LWW) * LWW;  // this thread's bitmap word
+        int my_count = 0;
+        for (int tau = 0; tau < nsteps; ++tau) {
+            const int c = tau & 3, si = c >> 1, sj = c & 1;
+            // Exact region after tau steps, clipped to the image interior,
+            // as lattice rows a (region row 2a + si) and columns b (2b + sj).
+            const int r_lo = max(tau + 1, 1 - ry0), r_hi = min(RH - 2 - tau, d.h - 2 - ry0);
+            const int c_lo = max(tau + 1, 1 - rx0), c_hi = min(RW - 2 - tau, d.w - 2 - rx0);
+            const int a_lo = (r_lo - si + 1) >> 1, a_hi = (r_hi - si) >> 1;
+            const int b_lo = (c_lo - sj + 1) >> 1, b_hi = (c_hi - sj) >> 1;
+            uint32_t take = 0u;
+            if (tid < CLASS_WORDS && wa >= a_lo && wa <= a_hi) {
+                const int lo = max(b_lo - 32 * wj, 0), hi = min(b_hi - 32 * wj, 31);
+                if (lo <= hi) {
+                    const uint32_t mask = (hi == 31 ? ~0u : ((2u << hi) - 1u)) & ~((1u << lo) - 1u);
+                    uint32_t* p = s_db + c * CLASS_WORDS + tid;
+                    const uint32_t w = *p;
+                    take = w & mask;
+                    if (take) *p = w & ~mask;
+                }
+            }
+            const int cnt = __popc(take);
+            int incl = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int v = __shfl_up(incl, o);
+                if (lane >= o) incl += v;
+            }
+            if (lane == 63) s_wsum[wave] = incl;
+            __syncthreads();
+            int base = 0, total = 0;
+#pragma unroll
+            for (int wv = 0; wv < NWAVE; ++wv) {
+                const int sv = s_wsum[wv];
+                base += wv < wave ? sv : 0;
+                total += sv;
+            }
+            if (take) {
+                int off = base + incl - cnt;
+                const int cell0 = wa * LAT_W + 32 * wj;
+                uint32_t t = take;
+                while (t) {
+                    s_list[off++] = (uint16_t)(cell0 + __ffs(t) - 1);
+                    t &= t - 1u;
+                }
+            }
+            __syncthreads();
+            bool inner = false;
+            for (int i = tid; i < total; i += NT) {
+                const int cell = s_list[i];
+                const int a = cell / LAT_W, b = cell - a * LAT_W;
+                const int lr = 2 * a + si, lc = 2 * b + sj;
+                uint16_t* p = s_img + lr * RWP + lc;
+                const uint32_t v = p[0];
+                const uint32_t nbv[8] = {p[1], p[-RWP + 1], p[-RWP], p[-RWP - 1],
+                                         p[-1], p[RWP - 1], p[RWP], p[RWP + 1]};
+                uint32_t alpha;
+                if (decide(v, nbv, lut, lambda, alpha)) {
+                    p[0] = (uint16_t)alpha;
+#pragma unroll
+                    for (int dy = -1; dy <= 1; ++dy) {
+                        const int y = lr + dy;
+#pragma unroll
+                        for (int dx = -1; dx <= 1; ++dx) {
+                            const int x = lc + dx;
+                            const int cc = ((y & 1) << 1) | (x & 1), bb = x >> 1;
+                            atomicOr(&s_db[cc * CLASS_WORDS + (y >> 1) * LWW + (bb >> 5)],
+                                     1u << (bb & 31));
+                        }
+                    }
+                    if (lr >= K && lr < K + TH && lc >= K && lc < K + TW) {
+                        ++my_count;
+                        inner = true;
+                        if constexpr (SEED) {
+                            if (tau >= nsteps - 4) {
+                                const int y = lr - K, x = lc - K;
+                                atomicOr(&s_bits[y * WPR + (x >> 5)], 1u << (x & 31));
+                            }
+                        }
+                    }
+                }
+            }
+            // One lane per wave that lowered an interior pixel records the step.
+            if (__ballot(inner) != 0ull && lane == 0) atomicMax(s_last, tau);
+            __syncthreads();
+        }
+
+        if (wide && d.dtype == 1) {
+            store_wide<uint8_t, TH, TW, RWP, K, K, NT>(d, static_cast<uint8_t*>(dst), gy0, gx0,
+                                                       s_img, tid);
+        } else if (wide) {
+            store_wide<uint16_t, TH, TW, RWP, K, K, NT>(d, static_cast<uint16_t*>(dst), gy0, gx0,
+                                                        s_img, tid);
+        } else {
+            const int ih = min(TH, d.h - gy0), iw = min(TW, d.w - gx0);
+            for (int idx = tid; idx < TH * TW; idx += NT) {
+                const int y = idx / TW, x = idx - y * TW;
+                if (y < ih && x < iw)
+                    store_px(dst, d.dtype, (int64_t)(gy0 + y) * d.pitch + (gx0 + x),
+                             s_img[(K + y) * RWP + (K + x)]);
+            }
+        }
+        if (my_count) atomicAdd(s_count, my_count);
+        __syncthreads();
+        if constexpr (SEED) {
+            if (sd != nullptr) {
+                for (int i = tid; i < TH * WPR; i += NT)
+                    sd->cur_bits[(int64_t)sd->g * TH * WPR + i] = s_bits[i];
+                if (tid == 0) sd->cur_round[sd->g] = sd->r;
+            }
+        }
+        last_tau = *s_last;
+        return *s_count;
+    }
+};
+
 template <int TH, int TW, int K, int NT, int VAR>
-using TileOf = typename std::conditional<VAR == kVarRegs, RTile<TH, TW, K, NT>,
-                                         Tile<TH, TW, K, NT, VAR == kVarSeeded>>::type;
+using TileOf = typename std::conditional<
+    VAR == kVarRegs, RTile<TH, TW, K, NT>,
+    typename std::conditional<VAR == kVarBits || VAR == kVarBitsSeeded,
+                              BTile<TH, TW, K, NT, VAR == kVarBitsSeeded>,
+                              Tile<TH, TW, K, NT, VAR == kVarSeeded>>::type>::type;
 
 // ----------------------------------------------------------------- k_round
 
 // One tile of one round (launch-per-round and cooperative engines).
 // Returns 1 when the tile was processed (active), 0 when skipped.  All NT
 // threads must call it together.
+// Queues tile g for launch round `next` (once per round).
+__device__ __forceinline__ void enqueue(const WorkList& wl, int g, int next)
+{
+    if (atomicMax(&wl.listed[g], next) < next) {
+        const int pos = atomicAdd(&wl.count[next % 3], 1);
+        wl.list[(next & 1) * wl.cap + pos] = g;
+    }
+}
+
 template <int TH, int TW, int K, int NT, int VAR>
 __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                           const int32_t* __restrict__ tile_img, int32_t* tile_state, int g,
                           int round, int ntiles, uint32_t* hist_bits, int32_t* hist_round,
                           uint16_t* s_img, uint8_t* s_dirty, uint32_t* s_bits, uint32_t* s_cw,
-                          const TopoEntry* s_lut, int* s_count, int* s_last)
+                          const TopoEntry* s_lut, int* s_count, int* s_last,
+                          const WorkList& wl)
 {
     using T = TileOf<TH, TW, K, NT, VAR>;
     const int tid = threadIdx.x;
@@ -700,7 +1121,7 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
         return 0;
     }
     Seed sd{};
-    const int64_t words = VAR == kVarSeeded ? (int64_t)ntiles * TH * T::WPR : 0;
+    const int64_t words = var_seeded(VAR) ? (int64_t)ntiles * TH * T::WPR : 0;
     sd.prev_bits = hist_bits + ((r + 1) & 1) * words;
     sd.prev_round = hist_round + ((r + 1) & 1) * ntiles;
     sd.cur_bits = hist_bits + (r & 1) * words;
@@ -714,7 +1135,7 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
     sd.g = g;
     int last_tau;
     const int count = T::run(v, gy0, gx0, t0, nsteps, src, dst, s_img, s_dirty, s_bits, s_cw,
-                             VAR == kVarSeeded ? &sd : nullptr, s_lut + d->adj * 256, s_count, s_last, tid,
+                             var_seeded(VAR) ? &sd : nullptr, s_lut + d->adj * 256, s_count, s_last, tid,
                              last_tau);
     if (tid == 0) {
         atomicAdd(&cnt[slot].tile_rounds, 1ull);
@@ -722,6 +1143,7 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
             __hip_atomic_store(&st[1], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             atomicAdd(&cnt[slot].lowerings, (unsigned long long)count);
             atomicMax(&cnt[slot].last_step, t0 + last_tau);
+            if (wl.list != nullptr) enqueue(wl, g, round + 1);
         }
         // Lowered during the last 4 steps: the 3x3 tile block must run the next
         // round (a tile whose whole block was quiet for 4 steps cannot change
@@ -735,6 +1157,7 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
                     if (x < 0 || x >= d->tiles_x) continue;
                     __hip_atomic_fetch_max(&tile_state[2 * (d->state0 + y * d->tiles_x + x)],
                                            r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (wl.list != nullptr) enqueue(wl, d->tile0 + y * d->tiles_x + x, round + 1);
                 }
             }
         }
@@ -747,20 +1170,25 @@ __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, I
                                               const int32_t* __restrict__ tile_img,
                                               int32_t* tile_last, int ntiles, int round,
                                               const TopoEntry* __restrict__ lut_g,
-                                              uint32_t* hist_bits, int32_t* hist_round)
+                                              uint32_t* hist_bits, int32_t* hist_round,
+                                              WorkList wl)
 {
     using T = TileOf<TH, TW, K, NT, VAR>;
     __shared__ __align__(16) uint16_t s_img[T::IMG_ELEMS];
-    __shared__ uint8_t s_dirty[T::DIRTY_ELEMS];
+    __shared__ __align__(16) uint8_t s_dirty[T::DIRTY_ELEMS];
     __shared__ uint32_t s_bits[T::BITS_WORDS];
     __shared__ uint32_t s_cw[T::CW_WORDS];
     __shared__ TopoEntry s_lut[512];
     __shared__ int s_count, s_last;
     for (int i = threadIdx.x; i < 512; i += NT) s_lut[i] = lut_g[i];
-    for (int g = blockIdx.x; g < ntiles; g += gridDim.x)
-        round_tile<TH, TW, K, NT, VAR>(imgs, cnt, tile_img, tile_last, g, round, ntiles, hist_bits,
-                                  hist_round, s_img, s_dirty, s_bits, s_cw, s_lut, &s_count,
-                                  &s_last);
+    const bool all = wl.list == nullptr || wl.full;
+    const int n = all ? ntiles : wl.count[round % 3];
+    if (wl.list != nullptr && blockIdx.x == 0 && threadIdx.x == 0) wl.count[(round + 2) % 3] = 0;
+    const int32_t* mine = all ? nullptr : wl.list + (round & 1) * wl.cap;
+    for (int i = blockIdx.x; i < n; i += gridDim.x)
+        round_tile<TH, TW, K, NT, VAR>(imgs, cnt, tile_img, tile_last, all ? i : mine[i], round,
+                                       ntiles, hist_bits, hist_round, s_img, s_dirty, s_bits,
+                                       s_cw, s_lut, &s_count, &s_last, wl);
 }
 
 // ------------------------------------------------------------------ k_coop
@@ -784,7 +1212,7 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
 {
     using T = TileOf<TH, TW, K, NT, VAR>;
     __shared__ __align__(16) uint16_t s_img[T::IMG_ELEMS];
-    __shared__ uint8_t s_dirty[T::DIRTY_ELEMS];
+    __shared__ __align__(16) uint8_t s_dirty[T::DIRTY_ELEMS];
     __shared__ uint32_t s_bits[T::BITS_WORDS];
     __shared__ uint32_t s_cw[T::CW_WORDS];
     __shared__ TopoEntry s_lut[512];
@@ -801,7 +1229,7 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
         for (int g = blockIdx.x; g < ntiles; g += gridDim.x)
             mine += round_tile<TH, TW, K, NT, VAR>(imgs, cnt, tile_img, tile_last, g, round, ntiles,
                                               hist_bits, hist_round, s_img, s_dirty, s_bits, s_cw,
-                                              s_lut, &s_count, &s_last);
+                                              s_lut, &s_count, &s_last, WorkList{});
         if (tid == 0 && mine) atomicAdd(&active[round % 3], mine);
         // Stores of every wave must be acknowledged before the grid barrier
         // publishes them.
@@ -838,23 +1266,22 @@ template <int TH, int TW, int K, int NT, int VAR>
 hipError_t launch_round_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                           const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
                           const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
-                          int32_t* hist_round)
+                          int32_t* hist_round, WorkList wl)
 {
     const int grid = max(1, min(ntiles, grid_blocks));
     hipLaunchKernelGGL((k_round<TH, TW, K, NT, VAR>), dim3(grid), dim3(NT), 0, stream, imgs, cnt,
-                       tile_img, tile_last, ntiles, round, lut, hist_bits, hist_round);
+                       tile_img, tile_last, ntiles, round, lut, hist_bits, hist_round, wl);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_init_state(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t* tile_last,
-                             int ntiles, int32_t* hist_round)
+                             int ntiles, int32_t* hist_round, WorkList wl)
 {
-    const int n = max(nimg, 2 * ntiles);
-    if (n <= 0) return hipSuccess;
+    const int n = max(max(nimg, 2 * ntiles), 3);
     hipLaunchKernelGGL(k_init_state, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                       stream, cnt, nimg, tile_last, ntiles, hist_round);
+                       stream, cnt, nimg, tile_last, ntiles, hist_round, wl);
     return hipGetLastError();
 }
 
@@ -892,6 +1319,20 @@ hipError_t launch_step(hipStream_t stream, const ImgDev* img_host, const ImgDev*
     X(48, 48, 16, 512, 0)   \
     X(32, 32, 16, 512, 0)   \
     X(128, 128, 16, 512, 0) \
+    X(128, 128, 16, 512, 1) \
+    X(64, 64, 16, 512, 1)   \
+    X(32, 32, 16, 256, 3)   \
+    X(64, 64, 16, 256, 3)   \
+    X(64, 64, 16, 256, 4)   \
+    X(128, 128, 16, 256, 4) \
+    X(32, 32, 16, 512, 3)   \
+    X(64, 64, 16, 512, 3)   \
+    X(64, 64, 16, 512, 4)   \
+    X(64, 64, 32, 512, 3)   \
+    X(64, 64, 32, 512, 4)   \
+    X(128, 128, 16, 512, 3) \
+    X(128, 128, 16, 512, 4) \
+    X(128, 128, 32, 512, 4) \
     X(64, 64, 16, 512, 2)   \
     X(32, 32, 16, 512, 2)   \
     X(16, 16, 8, 256, 2)    \
@@ -924,13 +1365,18 @@ static int lds_bytes(TileShape s)
 {
     if (s.var == kVarRegs) return (s.th + 2 * s.k + 2) * (s.tw + 2 * s.k + 2) * 2 + 4096 + 64;
     const int region = (s.th + 2 * s.k) * (s.tw + 2 * s.k);
-    const int hist = s.var == kVarSeeded
+    const int hist = var_seeded(s.var)
                          ? (s.th * (s.tw / 32) + (s.th + 2 * s.k) * ((s.tw + 2 * s.k + 31) / 32)) * 4
                          : 8;
+    if (s.var == kVarBits || s.var == kVarBitsSeeded) {
+        const int lat_h = (s.th + 2 * s.k) / 2, lat_w = (s.tw + 2 * s.k) / 2;
+        const int flags = 16 * lat_h * ((lat_w + 31) / 32) + 2 * lat_h * lat_w + 64;
+        return region * 2 + flags + hist + 4096 + 64;
+    }
     return region * 3 + hist + 4096 + 64;
 }
 
-int history_words(TileShape s) { return s.var == kVarSeeded ? s.th * (s.tw / 32) : 1; }
+int history_words(TileShape s) { return var_seeded(s.var) ? s.th * (s.tw / 32) : 1; }
 
 int round_blocks_per_cu(TileShape s)
 {
@@ -942,12 +1388,12 @@ int round_blocks_per_cu(TileShape s)
 hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                         const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
                         const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
-                        int32_t* hist_round)
+                        int32_t* hist_round, WorkList wl)
 {
 #define X(a, b, c, n, e)                                                                    \
     if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.var == e)  \
         return launch_round_t<a, b, c, n, e>(stream, imgs, cnt, tile_img, tile_last, ntiles, \
-                                             round, lut, grid_blocks, hist_bits, hist_round);
+                                             round, lut, grid_blocks, hist_bits, hist_round, wl);
     THIN_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;

@@ -119,7 +119,7 @@ struct thin_ctx {
 
     TopoEntry* d_lut = nullptr;
     uint64_t allocated = 0;        // bytes of scratch currently held
-    DevBuf twin, imgs, cnt, tile_img, tile_last, small, hist_bits, hist_round;
+    DevBuf twin, imgs, cnt, tile_img, tile_last, small, hist_bits, hist_round, wl_list, wl_meta;
     ImgCnt* h_snap[2] = {nullptr, nullptr};   // pinned snapshots of the counters
     size_t h_snap_cap = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -218,7 +218,7 @@ int ensure_snap(thin_ctx* ctx, size_t n)
 // Launches one round, bracketed by timing events when profiling.
 int timed_round(thin_ctx* ctx, size_t& ev_used, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                 const int32_t* tile_img, int32_t* tile_last, int ntiles, int round, int grid,
-                uint32_t* hist_bits, int32_t* hist_round)
+                uint32_t* hist_bits, int32_t* hist_round, thin::WorkList wl)
 {
     if (ctx->profile) {
         while (ctx->prof_ev.size() < ev_used + 2) {
@@ -229,7 +229,7 @@ int timed_round(thin_ctx* ctx, size_t& ev_used, TileShape shape, const ImgDev* i
         HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used], ctx->stream));
     }
     HIP_TRY(ctx, thin::launch_round(ctx->stream, shape, imgs, cnt, tile_img, tile_last, ntiles,
-                                    round, ctx->d_lut, grid, hist_bits, hist_round));
+                                    round, ctx->d_lut, grid, hist_bits, hist_round, wl));
     if (ctx->profile) {
         HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used + 1], ctx->stream));
         ev_used += 2;
@@ -270,16 +270,18 @@ int steps_cap(const thin_ctx* ctx)
     return s > (uint64_t)INT_MAX ? INT_MAX : (int)s;
 }
 
-TileShape choose_shape(const thin_ctx* ctx, int64_t total_pixels)
+TileShape choose_shape(const thin_ctx* ctx, int64_t total_pixels, int64_t images)
 {
     if (ctx->forced.th) return ctx->forced;
     // Small work lists are bound by the latency of each round: small tiles
     // with one cell per thread and register windows.  Large ones are bound by
-    // throughput: big tiles (less halo work) and 512-thread blocks, several
-    // per CU, so one block's staging overlaps another's steps.
+    // throughput: dense per-step work lists with seeded flags, in big tiles
+    // (less halo work) when the images are large, else in 64x64 tiles with
+    // 256-thread blocks, several per CU.
     if (total_pixels <= (int64_t)1 << 20) return TileShape{32, 32, 16, 1024, thin::kVarRegs};
-    if (total_pixels <= (int64_t)32 << 20) return TileShape{64, 64, 16, 512, thin::kVarFlags};
-    return TileShape{128, 128, 16, 512, thin::kVarFlags};
+    if (total_pixels >= ((int64_t)4 << 20) * std::max<int64_t>(images, 1))
+        return TileShape{128, 128, 16, 512, thin::kVarBitsSeeded};
+    return TileShape{64, 64, 16, 256, thin::kVarBitsSeeded};
 }
 
 void fill_stats(thin_stats* st, const ImgCnt& c, int steps_done, int max_steps, bool trivial)
@@ -314,7 +316,7 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
 {
     int64_t total_px = 0;
     for (int i : work) total_px += ims[i].h * ims[i].w;
-    const TileShape shape = choose_shape(ctx, total_px);
+    const TileShape shape = choose_shape(ctx, total_px, (int64_t)work.size());
     if (!thin::tile_shape_supported(shape))
         return fail(ctx, THIN_EINVAL, "unsupported tile shape %dx%d k=%d", shape.th, shape.tw, shape.k);
     const int K = shape.k;
@@ -378,10 +380,21 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
                                 hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(d_tile_img, plan.tile_img.data(), sizeof(int32_t) * ntiles,
                                 hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, nimg, d_tile_last, ntiles,
-                                         d_hist_round));
-
+    // Work lists: round 0 visits every tile, later rounds the tiles queued
+    // by the round before.
+    if ((rc = ensure(ctx, ctx->wl_list, sizeof(int32_t) * 2 * (size_t)ntiles))) return rc;
+    if ((rc = ensure(ctx, ctx->wl_meta, sizeof(int32_t) * (4 + (size_t)ntiles)))) return rc;
+    // (Only worth a longer dependency chain per visit when blocks visit
+    // several tiles each.)
     const int grid = ctx->num_cus * thin::round_blocks_per_cu(shape);
+    thin::WorkList wl{};
+    if (ntiles > 2 * grid) wl.list = static_cast<int32_t*>(ctx->wl_list.ptr);
+    wl.count = static_cast<int32_t*>(ctx->wl_meta.ptr);
+    wl.listed = wl.count + 4;
+    wl.cap = ntiles;
+    HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, nimg, d_tile_last, ntiles,
+                                         d_hist_round, wl));
+
     const int rounds_cap = (max_steps == INT_MAX) ? INT_MAX : (max_steps + K - 1) / K;
     size_t ev_used = 0;        // profiling events recorded by this call
     int launched = 0;          // rounds enqueued so far
@@ -401,8 +414,9 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
     while (!done) {
         const int n = std::min(chunk, rounds_cap - launched);
         for (int k = 0; k < n; ++k) {
+            wl.full = launched == 0;
             if ((rc = timed_round(ctx, ev_used, shape, d_imgs, d_cnt, d_tile_img, d_tile_last,
-                                  ntiles, launched, grid, d_hist_bits, d_hist_round)))
+                                  ntiles, launched, grid, d_hist_bits, d_hist_round, wl)))
                 return rc;
             ++launched;
         }
@@ -462,7 +476,7 @@ int run_coop(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
 {
     int64_t total_px = 0;
     for (int i : work) total_px += ims[i].h * ims[i].w;
-    const TileShape shape = choose_shape(ctx, total_px);
+    const TileShape shape = choose_shape(ctx, total_px, (int64_t)work.size());
     if (!thin::tile_shape_supported(shape))
         return fail(ctx, THIN_EINVAL, "unsupported tile shape %dx%d k=%d", shape.th, shape.tw, shape.k);
     const int K = shape.k;
@@ -528,7 +542,8 @@ int run_coop(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
                                 hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemsetAsync(d_small, 0, 4 * sizeof(int32_t), ctx->stream));
     HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, nimg, d_tile_last, ntiles,
-                                         static_cast<int32_t*>(ctx->hist_round.ptr)));
+                                         static_cast<int32_t*>(ctx->hist_round.ptr),
+                                         thin::WorkList{}));
     const int rounds_cap = (max_steps == INT_MAX) ? INT_MAX : (max_steps + K - 1) / K;
     size_t ev_used = 0;
     if (ctx->profile) {
@@ -604,7 +619,8 @@ int run_step_engine(thin_ctx* ctx, const thin_image* ims, const std::vector<int>
         ImgDev* d_img = static_cast<ImgDev*>(ctx->imgs.ptr);
         ImgCnt* d_cnt = static_cast<ImgCnt*>(ctx->cnt.ptr);
         HIP_TRY(ctx, hipMemcpyAsync(d_img, &d, sizeof d, hipMemcpyHostToDevice, ctx->stream));
-        HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, 1, nullptr, 0, nullptr));
+        HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, 1, nullptr, 0, nullptr,
+                                             thin::WorkList{}));
         int step = 0;
         for (;;) {
             for (int s = 0; s < 4 && step < max_steps; ++s, ++step)
@@ -744,7 +760,7 @@ int thin_destroy(thin_ctx* ctx)
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
     DevBuf* bufs[] = {&ctx->twin,       &ctx->imgs,        &ctx->cnt,        &ctx->tile_img,
-                      &ctx->tile_last,  &ctx->small,
+                      &ctx->tile_last,  &ctx->small,      &ctx->wl_list,    &ctx->wl_meta,
                       &ctx->hist_bits,  &ctx->hist_round,  &ctx->serve_twin, &ctx->serve_state,
                       &ctx->serve_cnt,  &ctx->serve_imgs,  &ctx->serve_tile_img};
     for (DevBuf* b : bufs)
@@ -821,8 +837,10 @@ int thin_serve_admit(thin_ctx* ctx, const thin_image* img, uint64_t tag)
     }
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if (!ctx->serve_ready) {
-        TileShape shape = choose_shape(ctx, (int64_t)16 << 20);
-        if (shape.var == thin::kVarSeeded) shape.var = thin::kVarFlags;
+        // Latency first: per-pixel flags in 64x64 tiles (the dense-list
+        // variants spend more time per step when little is flagged).
+        TileShape shape = ctx->forced.th ? ctx->forced : TileShape{64, 64, 16, 512, thin::kVarFlags};
+        shape.var = thin::var_unseeded(shape.var);
         if (!thin::tile_shape_supported(shape))
             return fail(ctx, THIN_EINVAL, "no compiled serving shape %dx%d k=%d", shape.th,
                         shape.tw, shape.k);
@@ -953,7 +971,7 @@ int thin_serve_step(thin_ctx* ctx, int32_t rounds, uint64_t* done_tags, thin_sta
                                   d_cnt, static_cast<int32_t*>(ctx->serve_tile_img.ptr), d_state,
                                   ntiles, ctx->serve_round + k, grid,
                                   static_cast<uint32_t*>(ctx->hist_bits.ptr),
-                                  static_cast<int32_t*>(ctx->hist_round.ptr))))
+                                  static_cast<int32_t*>(ctx->hist_round.ptr), thin::WorkList{})))
                 return rc;
         }
         ctx->serve_round += rounds;

@@ -104,15 +104,20 @@ def test_fuzz(case):
 
 # Every compiled (tile height, width, halo, threads, residency variant) shape:
 # variant 0 keeps per-pixel flags in LDS, 1 seeds them from the previous
-# round, 2 keeps 4x4 windows in registers.
+# round, 2 keeps 4x4 windows in registers, 3 keeps one flag bit per candidate
+# and examines dense lists, 4 seeds those bits from the previous round.
 ALL_SHAPES = ["16,16,8,256,0", "32,32,8,256,0", "32,32,8,512,0", "32,32,16,256,0",
               "32,32,16,512,0", "32,32,16,1024,0", "32,32,16,1024,1", "48,48,16,512,0",
               "64,64,8,512,0", "64,64,8,1024,0", "64,64,16,256,0", "64,64,16,512,0",
               "64,64,16,1024,0", "64,64,16,1024,1", "64,64,32,512,0", "64,64,32,1024,0",
-              "128,128,16,512,0",
+              "128,128,16,512,0", "128,128,16,512,1", "64,64,16,512,1",
               "16,16,8,256,2", "32,32,8,256,2", "32,32,16,256,2", "32,32,16,512,2",
               "32,32,16,1024,2", "32,32,32,1024,2", "64,64,16,512,2", "64,64,16,1024,2",
-              "64,64,32,1024,2"]
+              "64,64,32,1024,2",
+              "32,32,16,256,3", "32,32,16,512,3", "64,64,16,512,3", "64,64,16,512,4",
+              "64,64,16,256,3", "64,64,16,256,4", "128,128,16,256,4",
+              "64,64,32,512,3", "64,64,32,512,4", "128,128,16,512,3", "128,128,16,512,4",
+              "128,128,32,512,4"]
 
 
 @pytest.mark.parametrize("shape", ALL_SHAPES)
