@@ -94,13 +94,16 @@ def cpu_baseline(images, budget_s: float):
     return px / dt / 1e6, n, dt
 
 
-def _kernel_pass(ctx_kw, inputs, job_args, run):
+def _kernel_pass(ctx_kw, inputs, job_args, run, prepare=None):
     """Runs `run` over `inputs` with per-launch HIP events on the library's
-    stream; returns (launches, kernel_ms)."""
+    stream; returns (launches, kernel_ms).  `prepare(ctx)` runs first,
+    outside the measurement."""
     import torch
     from paper_1603_09180_amd import thin
 
     ctx = thin.Context(device=0, profile=True, **ctx_kw)
+    if prepare is not None:
+        prepare(ctx)
     torch.cuda.synchronize()
     ctx.profile(reset=True)
     for t in inputs:
@@ -111,7 +114,7 @@ def _kernel_pass(ctx_kw, inputs, job_args, run):
     return int(prof.launches), float(prof.kernel_ms)
 
 
-def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0):
+def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, graph=False):
     import numpy as np
     import torch
 
@@ -126,7 +129,7 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0):
     inputs = [src.clone() for _ in range(warmup + steps)]
     torch.cuda.synchronize()
     ctx_kw = dict(tile=tile, steps_per_round=k, engine=engine)
-    ctx = thin.Context(device=0, **ctx_kw)
+    ctx = thin.Context(device=0, graph=graph, **ctx_kw)
     for i in range(warmup):
         ctx.run(inputs[i], job.lam, job.adj)
     torch.cuda.synchronize()
@@ -174,7 +177,7 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0):
         "data": "synthetic",
         "config": {"workload": name, "h": h, "w": w, "lambda": job.lam,
                    "adjacency": "8,4" if job.adj == 0 else "4,8", "images_per_step": 1,
-                   "path": "plain (thin_run)",
+                   "path": "plain (thin_run)", "graph": graph,
                    "engine": {0: "auto", 1: "tiled", 2: "step", 3: "persistent",
                               4: "cooperative"}[engine]},
         "images_per_s": round(steps / elapsed, 2),
@@ -224,7 +227,7 @@ def copy_calibration(nbytes=1 << 28, reps=20):
             "GBps": round(2 * nbytes * reps / dt / 1e9, 1)}
 
 
-def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512):
+def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512, tune=True, graph=False):
     import numpy as np
     import torch
 
@@ -238,7 +241,12 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512):
     lams = [j.lam for j in jobs]
     adjs = [j.adj for j in jobs]
     ctx_kw = dict(tile=tile, steps_per_round=k, engine=engine)
-    ctx = thin.Context(device=0, **ctx_kw)
+    ctx = thin.Context(device=0, graph=graph, **ctx_kw)
+    tuned = None
+    if tune and not tile:
+        # tile shape and steps per residency chosen by the autotuner, on
+        # copies of the batch, outside the timed region
+        tuned = ctx.autotune(srcs, lams, adjs, reps=2)
     sets = [[s.clone() for s in srcs] for _ in range(warmup + steps)]
     torch.cuda.synchronize()
     for i in range(warmup):
@@ -258,8 +266,11 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512):
     torch.cuda.synchronize()
     p1 = time.perf_counter()
     ctx.close()
+    def retune(c):
+        if tuned is not None:
+            c.autotune(srcs, lams, adjs, reps=2)  # the same size class, tuned again
     launches, kernel_ms = _kernel_pass(ctx_kw, [[s.clone() for s in srcs]], (lams, adjs),
-                                       lambda c, ts, l, a: c.run_batch(ts, l, a))
+                                       lambda c, ts, l, a: c.run_batch(ts, l, a), prepare=retune)
     # bit-exactness on a sample the oracle finishes quickly: the 12 smallest
     # images and every 16th image of at most 0.3 Mpixel
     order = sorted(range(n_images), key=lambda i: Fs[i].size)
@@ -286,7 +297,13 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512):
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": "batch_512", "images_per_step": n_images,
                    "sides": "log-uniform 64..2048", "lambda": "{0,5,20,50}",
-                   "adjacency": "8,4", "path": "batched (thin_run_batch)"},
+                   "adjacency": "8,4", "path": "batched (thin_run_batch)",
+                   "graph": graph,
+                   "autotuned": None if tuned is None else {
+                       "tile": list(tuned["tile"]), "steps_per_round": tuned["steps_per_round"],
+                       "threads": tuned["threads"], "variant": tuned["variant"],
+                       "candidates": tuned["candidates"], "tuned_ms": round(tuned["ms"], 3),
+                       "untuned_ms": round(tuned["default_ms"], 3)}},
         "images_per_s": round(n_images * steps / elapsed, 2),
         "plain_images_per_s": round(n_images / (p1 - p0), 2),
         "plain_mpixel_per_s": round(total_px / (p1 - p0) / 1e6, 3),
@@ -437,6 +454,10 @@ def main():
                     help="CPU budget of the oracle baseline (0 disables it)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--k", type=int, default=0)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batch_512: skip the tile-shape autotuner")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay chunks of rounds as HIP graphs")
     ap.add_argument("--engine", type=int, default=0,
                     help="0 auto, 1 tiled, 2 step, 3 persistent (disabled), 4 cooperative")
     args = ap.parse_args()
@@ -459,12 +480,12 @@ def main():
                             rounds_per_step=args.serve_rounds)
     elif args.workload == "batch_512":
         out = bench_batch(args.steps, args.warmup, args.cpu_seconds, args.tile, args.k,
-                          args.engine)
+                          args.engine, tune=not args.no_tune, graph=args.graph)
     else:
         job = {"ridges_512": synth.ridges_512, "blobs_128": synth.blobs_128,
                "blobs_8192_u16": synth.blobs_8192_u16}[args.workload]()
         out = bench_single(job, args.workload, args.steps, args.warmup, args.cpu_seconds,
-                           args.tile, args.k, args.engine)
+                           args.tile, args.k, args.engine, graph=args.graph)
     print(json.dumps(out), flush=True)
 
 

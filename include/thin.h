@@ -93,7 +93,9 @@ typedef struct thin_config {
 
 /* thin_config.flags */
 enum {
-    THIN_FLAG_PROFILE = 1       /* time every round kernel with HIP events (see thin_profile) */
+    THIN_FLAG_PROFILE = 1,      /* time every round kernel with HIP events (see thin_profile) */
+    THIN_FLAG_GRAPH = 2         /* tiled engine: replay chunks of rounds as HIP graphs
+                                   (ignored while THIN_FLAG_PROFILE is set) */
 };
 
 typedef struct thin_profile_info {
@@ -165,6 +167,29 @@ int thin_serve_admit(thin_ctx* ctx, const thin_image* img, uint64_t tag);
  * launched rounds are done. */
 int thin_serve_step(thin_ctx* ctx, int32_t rounds, uint64_t* done_tags, thin_stats* done_stats,
                     int32_t cap, int32_t* n_done, int32_t* n_resident);
+
+/* Result of thin_autotune: the chosen tile shape and its time. */
+typedef struct thin_tune_result {
+    int32_t tile_h, tile_w;     /* tile interior */
+    int32_t steps_per_round;    /* parity steps per residency (halo width) */
+    int32_t threads;            /* threads per tile */
+    int32_t variant;            /* residency variant (0..4) */
+    int32_t candidates;         /* shapes timed */
+    double ms;                  /* best wall time of one run over the images, chosen shape */
+    double default_ms;          /* the same with the untuned choice */
+} thin_tune_result;
+
+/* Tile-shape autotuner for the tiled engine.  Runs the images (copies of
+ * them: the caller's buffers are left untouched) once with every compiled
+ * tile shape, re-times the fastest few `reps` times, and makes the fastest
+ * the context's shape for later work lists of the same size class (total
+ * pixels and pixels per image, each rounded down to a power of two).  The
+ * results of every shape are identical; only the time differs.  The copies
+ * are freed before the call returns.  out may be NULL.  Returns THIN_OK,
+ * THIN_EINVAL (bad arguments, nothing to tune), THIN_ENOMEM or
+ * THIN_EDEVICE. */
+int thin_autotune(thin_ctx* ctx, const thin_image* imgs, int32_t n, int32_t reps,
+                  thin_tune_result* out);
 
 /* Releases the context and all scratch it owns (NULL is accepted).
  * Never frees caller images. */

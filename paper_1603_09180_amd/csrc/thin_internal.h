@@ -36,7 +36,7 @@ struct ImgCnt {
 
 // Tiles a round launch visits.  With list == nullptr every tile is visited.
 // Otherwise launch round R visits list[(R & 1) * cap + i] for i < count[R % 3]
-// (every tile when full != 0), and a tile appends the tiles that must be
+// (every tile when R == full), and a tile appends the tiles that must be
 // visited in round R + 1 (its 3x3 tile block when it lowered something during
 // its last 4 steps, itself when it lowered anything) to the other half,
 // deduplicated by listed[g] = last round g was queued for.  count[(R + 2) % 3]
@@ -46,7 +46,7 @@ struct WorkList {
     int32_t* count;
     int32_t* listed;
     int32_t cap;
-    int32_t full;
+    int32_t full;    // the launch round that visits every tile (-1: none)
 };
 
 // Connectivity table entry for an upper-neighbour mask (see thin_topology_table).
@@ -91,10 +91,14 @@ TileShape complete_shape(int th, int tw, int k);
 // Clears counters and tile state; with wl.list, listed[] = -1 and counts 0.
 hipError_t launch_init_state(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t* tile_last,
                              int ntiles, int32_t* hist_round, WorkList wl);
+// The launch's round is `round`, plus *round_base when round_base is not
+// null (graph replays: the same launches serve every chunk of rounds).
 hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                         const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
                         const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
-                        int32_t* hist_round, WorkList wl);
+                        int32_t* hist_round, WorkList wl, const int32_t* round_base);
+// *round_base += n (the last node of a chunk graph).
+hipError_t launch_advance(hipStream_t stream, int32_t* round_base, int n);
 // Words of one tile's change bitmap (two copies of ntiles bitmaps are needed).
 int history_words(TileShape s);
 hipError_t launch_step(hipStream_t stream, const ImgDev* img_host, const ImgDev* img_dev,
@@ -106,6 +110,8 @@ hipError_t launch_coop(hipStream_t stream, TileShape shape, const ImgDev* imgs, 
                        const TopoEntry* lut, int32_t* active, int32_t* rounds_out,
                        int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round);
 bool tile_shape_supported(TileShape s);
+// Every compiled shape: writes up to cap of them to out, returns the count.
+int compiled_shapes(TileShape* out, int cap);
 int round_blocks_per_cu(TileShape s);
 
 }  // namespace thin

@@ -117,6 +117,11 @@ __global__ void k_init_state(ImgCnt* cnt, int nimg, int32_t* tile_last, int ntil
     if (tile_last && i < 2 * ntiles) tile_last[i] = -1;
 }
 
+__global__ void k_advance(int32_t* round_base, int n)
+{
+    if (threadIdx.x == 0) *round_base += n;
+}
+
 // ------------------------------------------------------------------ k_step
 
 template <typename T>
@@ -1171,9 +1176,10 @@ __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, I
                                               int32_t* tile_last, int ntiles, int round,
                                               const TopoEntry* __restrict__ lut_g,
                                               uint32_t* hist_bits, int32_t* hist_round,
-                                              WorkList wl)
+                                              WorkList wl, const int32_t* round_base)
 {
     using T = TileOf<TH, TW, K, NT, VAR>;
+    if (round_base != nullptr) round += *round_base;
     __shared__ __align__(16) uint16_t s_img[T::IMG_ELEMS];
     __shared__ __align__(16) uint8_t s_dirty[T::DIRTY_ELEMS];
     __shared__ uint32_t s_bits[T::BITS_WORDS];
@@ -1181,7 +1187,7 @@ __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, I
     __shared__ TopoEntry s_lut[512];
     __shared__ int s_count, s_last;
     for (int i = threadIdx.x; i < 512; i += NT) s_lut[i] = lut_g[i];
-    const bool all = wl.list == nullptr || wl.full;
+    const bool all = wl.list == nullptr || round == wl.full;
     const int n = all ? ntiles : wl.count[round % 3];
     if (wl.list != nullptr && blockIdx.x == 0 && threadIdx.x == 0) wl.count[(round + 2) % 3] = 0;
     const int32_t* mine = all ? nullptr : wl.list + (round & 1) * wl.cap;
@@ -1266,11 +1272,12 @@ template <int TH, int TW, int K, int NT, int VAR>
 hipError_t launch_round_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                           const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
                           const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
-                          int32_t* hist_round, WorkList wl)
+                          int32_t* hist_round, WorkList wl, const int32_t* round_base)
 {
     const int grid = max(1, min(ntiles, grid_blocks));
     hipLaunchKernelGGL((k_round<TH, TW, K, NT, VAR>), dim3(grid), dim3(NT), 0, stream, imgs, cnt,
-                       tile_img, tile_last, ntiles, round, lut, hist_bits, hist_round, wl);
+                       tile_img, tile_last, ntiles, round, lut, hist_bits, hist_round, wl,
+                       round_base);
     return hipGetLastError();
 }
 
@@ -1282,6 +1289,12 @@ hipError_t launch_init_state(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t*
     const int n = max(max(nimg, 2 * ntiles), 3);
     hipLaunchKernelGGL(k_init_state, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
                        stream, cnt, nimg, tile_last, ntiles, hist_round, wl);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(hipStream_t stream, int32_t* round_base, int n)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, stream, round_base, n);
     return hipGetLastError();
 }
 
@@ -1352,6 +1365,17 @@ bool tile_shape_supported(TileShape s)
     return false;
 }
 
+int compiled_shapes(TileShape* out, int cap)
+{
+    int n = 0;
+#define X(a, b, c, t, e)                                  \
+    if (n < cap && out) out[n] = TileShape{a, b, c, t, e}; \
+    ++n;
+    THIN_SHAPES(X)
+#undef X
+    return n;
+}
+
 TileShape complete_shape(int th, int tw, int k)
 {
 #define X(a, b, c, n, e) \
@@ -1388,12 +1412,13 @@ int round_blocks_per_cu(TileShape s)
 hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                         const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
                         const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
-                        int32_t* hist_round, WorkList wl)
+                        int32_t* hist_round, WorkList wl, const int32_t* round_base)
 {
 #define X(a, b, c, n, e)                                                                    \
     if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.var == e)  \
         return launch_round_t<a, b, c, n, e>(stream, imgs, cnt, tile_img, tile_last, ntiles, \
-                                             round, lut, grid_blocks, hist_bits, hist_round, wl);
+                                             round, lut, grid_blocks, hist_bits, hist_round, wl, \
+                                             round_base);
     THIN_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;

@@ -13,6 +13,7 @@
 // index of the last step that lowered something: P = last_step / 4 + 2, or 1
 // when nothing was ever lowered (the final pass without change is counted).
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cstdarg>
 #include <cstdio>
@@ -144,6 +145,14 @@ struct thin_ctx {
     DevBuf serve_twin, serve_state, serve_cnt, serve_imgs, serve_tile_img;
     ImgCnt* serve_snap = nullptr;  // pinned copy of all counter slots
 
+    // graph mode (THIN_FLAG_GRAPH): instantiated chunk graphs by launch parameters
+    bool graph = false;
+    hipStream_t cap_stream = nullptr;
+    std::map<std::vector<uint64_t>, hipGraphExec_t> graphs;
+
+    // autotuned shapes by size class (log2 total pixels, log2 pixels per image)
+    std::map<std::pair<int, int>, TileShape> tuned;
+
     std::string last_error;
 };
 
@@ -229,7 +238,7 @@ int timed_round(thin_ctx* ctx, size_t& ev_used, TileShape shape, const ImgDev* i
         HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used], ctx->stream));
     }
     HIP_TRY(ctx, thin::launch_round(ctx->stream, shape, imgs, cnt, tile_img, tile_last, ntiles,
-                                    round, ctx->d_lut, grid, hist_bits, hist_round, wl));
+                                    round, ctx->d_lut, grid, hist_bits, hist_round, wl, nullptr));
     if (ctx->profile) {
         HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used + 1], ctx->stream));
         ev_used += 2;
@@ -270,9 +279,26 @@ int steps_cap(const thin_ctx* ctx)
     return s > (uint64_t)INT_MAX ? INT_MAX : (int)s;
 }
 
+int floor_log2(int64_t v)
+{
+    int l = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++l;
+    }
+    return l;
+}
+
+std::pair<int, int> size_class(int64_t total_pixels, int64_t images)
+{
+    return {floor_log2(total_pixels), floor_log2(total_pixels / std::max<int64_t>(images, 1))};
+}
+
 TileShape choose_shape(const thin_ctx* ctx, int64_t total_pixels, int64_t images)
 {
     if (ctx->forced.th) return ctx->forced;
+    auto it = ctx->tuned.find(size_class(total_pixels, images));
+    if (it != ctx->tuned.end()) return it->second;
     // Small work lists are bound by the latency of each round: small tiles
     // with one cell per thread and register windows.  Large ones are bound by
     // throughput: dense per-step work lists with seeded flags, in big tiles
@@ -311,6 +337,42 @@ struct Plan {
     std::vector<int32_t> tile_img;
     std::vector<int> src_index;     // position in the caller's array
 };
+
+// The instantiated graph for `key`, capturing `record` on the context's
+// capture stream the first time.
+template <typename F>
+int chunk_graph(thin_ctx* ctx, const std::vector<uint64_t>& key, F record, hipGraphExec_t* out)
+{
+    auto it = ctx->graphs.find(key);
+    if (it != ctx->graphs.end()) {
+        *out = it->second;
+        return THIN_OK;
+    }
+    if (ctx->graphs.size() >= 64) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+        ctx->graphs.clear();
+    }
+    if (!ctx->cap_stream)
+        HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    const hipError_t e = record(ctx->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(ctx, THIN_EDEVICE, "graph capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t ge = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e3 != hipSuccess) return fail(ctx, THIN_EDEVICE, "graph instantiation failed: %s",
+                                      hipGetErrorString(e3));
+    ctx->graphs[key] = ge;
+    *out = ge;
+    return THIN_OK;
+}
 
 int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work, thin_stats* stats)
 {
@@ -380,6 +442,7 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
                                 hipMemcpyHostToDevice, ctx->stream));
     HIP_TRY(ctx, hipMemcpyAsync(d_tile_img, plan.tile_img.data(), sizeof(int32_t) * ntiles,
                                 hipMemcpyHostToDevice, ctx->stream));
+    if ((rc = ensure(ctx, ctx->small, 64))) return rc;
     // Work lists: round 0 visits every tile, later rounds the tiles queued
     // by the round before.
     if ((rc = ensure(ctx, ctx->wl_list, sizeof(int32_t) * 2 * (size_t)ntiles))) return rc;
@@ -388,6 +451,7 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
     // several tiles each.)
     const int grid = ctx->num_cus * thin::round_blocks_per_cu(shape);
     thin::WorkList wl{};
+    wl.full = 0;
     if (ntiles > 2 * grid) wl.list = static_cast<int32_t*>(ctx->wl_list.ptr);
     wl.count = static_cast<int32_t*>(ctx->wl_meta.ptr);
     wl.listed = wl.count + 4;
@@ -411,14 +475,48 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
         }
         return true;
     };
+    // Graph mode: a chunk of rounds is one graph replay; the launches read
+    // their round from a device counter that the graph's last node advances.
+    const bool use_graph = ctx->graph && !ctx->profile;
+    int32_t* d_round = static_cast<int32_t*>(ctx->small.ptr) + 8;
+    if (use_graph) HIP_TRY(ctx, hipMemsetAsync(d_round, 0, sizeof(int32_t), ctx->stream));
+    auto record_rounds = [&](hipStream_t st, int count) -> hipError_t {
+        for (int k = 0; k < count; ++k) {
+            const hipError_t e = thin::launch_round(st, shape, d_imgs, d_cnt, d_tile_img,
+                                                    d_tile_last, ntiles, k, ctx->d_lut, grid,
+                                                    d_hist_bits, d_hist_round, wl, d_round);
+            if (e != hipSuccess) return e;
+        }
+        return thin::launch_advance(st, d_round, count);
+    };
     while (!done) {
         const int n = std::min(chunk, rounds_cap - launched);
-        for (int k = 0; k < n; ++k) {
-            wl.full = launched == 0;
-            if ((rc = timed_round(ctx, ev_used, shape, d_imgs, d_cnt, d_tile_img, d_tile_last,
-                                  ntiles, launched, grid, d_hist_bits, d_hist_round, wl)))
-                return rc;
-            ++launched;
+        if (use_graph) {
+            hipGraphExec_t ge = nullptr;
+            if (n == chunk) {
+                const std::vector<uint64_t> key = {
+                    (uint64_t)shape.th, (uint64_t)shape.tw, (uint64_t)shape.k, (uint64_t)shape.nt,
+                    (uint64_t)shape.var, (uint64_t)ntiles, (uint64_t)grid, (uint64_t)n,
+                    (uint64_t)(uintptr_t)d_imgs, (uint64_t)(uintptr_t)d_cnt,
+                    (uint64_t)(uintptr_t)d_tile_img, (uint64_t)(uintptr_t)d_tile_last,
+                    (uint64_t)(uintptr_t)d_hist_bits, (uint64_t)(uintptr_t)d_hist_round,
+                    (uint64_t)(uintptr_t)wl.list, (uint64_t)(uintptr_t)wl.count,
+                    (uint64_t)(uintptr_t)ctx->d_lut, (uint64_t)(uintptr_t)d_round};
+                if ((rc = chunk_graph(ctx, key, [&](hipStream_t st) { return record_rounds(st, n); },
+                                      &ge)))
+                    return rc;
+                HIP_TRY(ctx, hipGraphLaunch(ge, ctx->stream));
+            } else {
+                HIP_TRY(ctx, record_rounds(ctx->stream, n));
+            }
+            launched += n;
+        } else {
+            for (int k = 0; k < n; ++k) {
+                if ((rc = timed_round(ctx, ev_used, shape, d_imgs, d_cnt, d_tile_img, d_tile_last,
+                                      ntiles, launched, grid, d_hist_bits, d_hist_round, wl)))
+                    return rc;
+                ++launched;
+            }
         }
         const int slot = (pending < 0) ? 0 : 1 - pending;
         HIP_TRY(ctx, hipMemcpyAsync(ctx->h_snap[slot], d_cnt, sizeof(ImgCnt) * nimg,
@@ -663,6 +761,140 @@ int run_images(thin_ctx* ctx, const thin_image* ims, int n, thin_stats* stats)
     return run_tiled(ctx, ims, work, stats);
 }
 
+// One tiled run over `work` of ims with `shape` forced; wall time in ms
+// (the run synchronises the stream before returning).
+int timed_run(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work, TileShape shape,
+              double& ms)
+{
+    const TileShape saved = ctx->forced;
+    ctx->forced = shape;
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = run_tiled(ctx, ims, work, nullptr);
+    const auto t1 = std::chrono::steady_clock::now();
+    ctx->forced = saved;
+    if (rc == THIN_ELIMIT) rc = THIN_OK;
+    ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    return rc;
+}
+
+int autotune(thin_ctx* ctx, const thin_image* imgs, int n, int reps, thin_tune_result* out)
+{
+    if (n <= 0 || !imgs || reps < 1) return fail(ctx, THIN_EINVAL, "bad autotune arguments");
+    for (int i = 0; i < n; ++i) {
+        const int rc = validate(ctx, imgs[i]);
+        if (rc) return rc;
+    }
+    // Contiguous copies of the images that matter: pristine and working.
+    std::vector<thin_image> work_img;
+    std::vector<size_t> off;
+    size_t bytes = 0;
+    int64_t total_px = 0;
+    for (int i = 0; i < n; ++i) {
+        if (imgs[i].h < 3 || imgs[i].w < 3) continue;
+        thin_image c = imgs[i];
+        c.pitch_elems = c.w;
+        off.push_back(bytes);
+        bytes += ((size_t)c.h * (size_t)c.w * (c.dtype == THIN_U8 ? 1 : 2) + 255) & ~size_t(255);
+        total_px += c.h * c.w;
+        work_img.push_back(c);
+    }
+    if (work_img.empty()) return fail(ctx, THIN_EINVAL, "no image of at least 3x3 to tune on");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    void *pristine = nullptr, *scratch = nullptr;
+    if (hipMalloc(&pristine, bytes) != hipSuccess || hipMalloc(&scratch, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        if (pristine) (void)hipFree(pristine);
+        return fail(ctx, THIN_ENOMEM, "autotune copies of %zu bytes", 2 * bytes);
+    }
+    int rc = THIN_OK;
+    std::vector<int> work;
+    for (size_t k = 0, j = 0; k < (size_t)n; ++k) {
+        const thin_image& im = imgs[k];
+        if (im.h < 3 || im.w < 3) continue;
+        const size_t bpp = im.dtype == THIN_U8 ? 1 : 2;
+        const size_t pitch = (size_t)(im.pitch_elems ? im.pitch_elems : im.w) * bpp;
+        if (hipMemcpy2DAsync(static_cast<char*>(pristine) + off[j], (size_t)im.w * bpp, im.image,
+                             pitch, (size_t)im.w * bpp, (size_t)im.h, hipMemcpyDeviceToDevice,
+                             ctx->stream) != hipSuccess) {
+            rc = fail(ctx, THIN_EDEVICE, "autotune copy failed");
+            break;
+        }
+        work_img[j].image = static_cast<char*>(scratch) + off[j];
+        work.push_back((int)j);
+        ++j;
+    }
+    auto run_one = [&](TileShape shape, double& ms) -> int {
+        if (hipMemcpyAsync(scratch, pristine, bytes, hipMemcpyDeviceToDevice, ctx->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(ctx->stream) != hipSuccess)
+            return fail(ctx, THIN_EDEVICE, "autotune copy failed");
+        return timed_run(ctx, work_img.data(), work, shape, ms);
+    };
+    thin_tune_result res{};
+    TileShape best{0, 0, 0, 0, 0};
+    if (rc == THIN_OK) {
+        // Untuned choice first (also warms the context's buffers).
+        const auto cls = size_class(total_px, (int64_t)work_img.size());
+        const auto prev = ctx->tuned.find(cls);
+        TileShape prev_shape{0, 0, 0, 0, 0};
+        if (prev != ctx->tuned.end()) {
+            prev_shape = prev->second;
+            ctx->tuned.erase(prev);
+        }
+        const TileShape dflt = choose_shape(ctx, total_px, (int64_t)work_img.size());
+        double ms = 0.0;
+        if ((rc = run_one(dflt, ms)) == THIN_OK) rc = run_one(dflt, ms);
+        res.default_ms = ms;
+        std::vector<TileShape> shapes(thin::compiled_shapes(nullptr, 0));
+        thin::compiled_shapes(shapes.data(), (int)shapes.size());
+        std::vector<std::pair<double, TileShape>> timed;
+        for (const TileShape& sh : shapes) {
+            if (rc) break;
+            double t = 0.0;
+            const int r = run_one(sh, t);
+            if (r == THIN_EDEVICE) {
+                rc = r;
+                break;
+            }
+            if (r == THIN_OK) timed.push_back({t, sh});
+        }
+        std::sort(timed.begin(), timed.end(),
+                  [](const std::pair<double, TileShape>& a, const std::pair<double, TileShape>& b) {
+                      return a.first < b.first;
+                  });
+        const size_t finalists = std::min<size_t>(timed.size(), 3);
+        for (size_t f = 0; f < finalists && rc == THIN_OK; ++f)
+            for (int k = 1; k < reps && rc == THIN_OK; ++k) {
+                double t = 0.0;
+                rc = run_one(timed[f].second, t);
+                timed[f].first = std::min(timed[f].first, t);
+            }
+        if (rc == THIN_OK && !timed.empty()) {
+            size_t b = 0;
+            for (size_t f = 1; f < finalists; ++f)
+                if (timed[f].first < timed[b].first) b = f;
+            best = timed[b].second;
+            res.ms = timed[b].first;
+            res.candidates = (int32_t)timed.size();
+            ctx->tuned[cls] = best;
+        } else if (prev_shape.th) {
+            ctx->tuned[cls] = prev_shape;
+        }
+    }
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipFree(pristine);
+    (void)hipFree(scratch);
+    if (rc) return rc;
+    if (!best.th) return fail(ctx, THIN_EDEVICE, "no tile shape ran");
+    res.tile_h = best.th;
+    res.tile_w = best.tw;
+    res.steps_per_round = best.k;
+    res.threads = best.nt;
+    res.variant = best.var;
+    if (out) *out = res;
+    return THIN_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------- ABI
@@ -704,6 +936,7 @@ int thin_create(thin_ctx** out, const thin_config* cfg)
     ctx->max_passes = c.max_passes;
     ctx->forced = forced;
     ctx->profile = (c.flags & THIN_FLAG_PROFILE) != 0;
+    ctx->graph = (c.flags & THIN_FLAG_GRAPH) != 0;
     int rc = THIN_OK;
     do {
         if (hipSetDevice(c.device) != hipSuccess) { rc = THIN_EDEVICE; break; }
@@ -753,6 +986,13 @@ int thin_run_batch(thin_ctx* ctx, const thin_image* imgs, int32_t n, thin_stats*
     return run_images(ctx, imgs, n, stats);
 }
 
+int thin_autotune(thin_ctx* ctx, const thin_image* imgs, int32_t n, int32_t reps,
+                  thin_tune_result* out)
+{
+    if (!ctx) return THIN_EINVAL;
+    return autotune(ctx, imgs, n, reps, out);
+}
+
 int thin_destroy(thin_ctx* ctx)
 {
     if (!ctx) return THIN_OK;
@@ -772,6 +1012,8 @@ int thin_destroy(thin_ctx* ctx)
     }
     for (hipEvent_t e : ctx->prof_ev) (void)hipEventDestroy(e);
     if (ctx->serve_snap) (void)hipHostFree(ctx->serve_snap);
+    for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return THIN_OK;
 }

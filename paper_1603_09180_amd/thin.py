@@ -20,10 +20,12 @@ THIN_ADJ_8_4, THIN_ADJ_4_8 = 0, 1
 THIN_ENGINE_AUTO, THIN_ENGINE_TILED, THIN_ENGINE_STEP, THIN_ENGINE_PERSIST, THIN_ENGINE_COOP = (
     0, 1, 2, 3, 4)
 THIN_FLAG_PROFILE = 1
+THIN_FLAG_GRAPH = 2
 
 EXPORTED = [
     "thin_create", "thin_run", "thin_run_batch", "thin_serve_admit", "thin_serve_step",
     "thin_destroy", "thin_strerror", "thin_last_error", "thin_profile", "thin_topology_table",
+    "thin_autotune",
 ]
 
 
@@ -78,6 +80,19 @@ class thin_image(ctypes.Structure):
     ]
 
 
+class thin_tune_result(ctypes.Structure):
+    _fields_ = [
+        ("tile_h", ctypes.c_int32),
+        ("tile_w", ctypes.c_int32),
+        ("steps_per_round", ctypes.c_int32),
+        ("threads", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("ms", ctypes.c_double),
+        ("default_ms", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -115,6 +130,9 @@ def load_library(path: str = LIB_PATH):
     lib.thin_profile.restype = ctypes.c_int
     lib.thin_topology_table.argtypes = [ctypes.c_int32, P(ctypes.c_uint32), ctypes.c_int32]
     lib.thin_topology_table.restype = ctypes.c_int
+    lib.thin_autotune.argtypes = [ctypes.c_void_p, P(thin_image), ctypes.c_int32, ctypes.c_int32,
+                                  P(thin_tune_result)]
+    lib.thin_autotune.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -236,7 +254,7 @@ class Context:
 
     def __init__(self, device: int = 0, stream=None, engine: int = THIN_ENGINE_AUTO,
                  max_device_bytes: int = 0, max_passes: int = 0, tile: int = 0,
-                 steps_per_round: int = 0, profile: bool = False):
+                 steps_per_round: int = 0, profile: bool = False, graph: bool = False):
         import torch
 
         if stream is None:
@@ -249,7 +267,7 @@ class Context:
         cfg.max_passes = max_passes
         cfg.tile = tile
         cfg.steps_per_round = steps_per_round
-        cfg.flags = THIN_FLAG_PROFILE if profile else 0
+        cfg.flags = (THIN_FLAG_PROFILE if profile else 0) | (THIN_FLAG_GRAPH if graph else 0)
         self.device = device
         self.stream = stream
         self.handle = thin_create(cfg)
@@ -297,6 +315,20 @@ class Context:
         rc = thin_run_batch(self.handle, arr, n, st)
         self._check(rc, "thin_run_batch", allow_limit)
         return [Stats.of(st[i]) for i in range(n)]
+
+    def autotune(self, tensors, lams, adjs, reps: int = 2) -> dict:
+        """Times every compiled tile shape on copies of these images and makes
+        the fastest this context's choice for work lists of their size class."""
+        n = len(tensors)
+        arr = (thin_image * max(n, 1))()
+        for i, (t, lam, adj) in enumerate(zip(tensors, lams, adjs)):
+            arr[i] = describe(t, lam, adj)
+        res = thin_tune_result()
+        rc = load_library().thin_autotune(self.handle, arr, n, reps, ctypes.byref(res))
+        self._check(rc, "thin_autotune")
+        return {"tile": (res.tile_h, res.tile_w), "steps_per_round": res.steps_per_round,
+                "threads": res.threads, "variant": res.variant, "candidates": res.candidates,
+                "ms": res.ms, "default_ms": res.default_ms}
 
     # ---------------------------------------------------------- serving
 

@@ -230,3 +230,41 @@ def test_persistent_engine_reports_disabled():
         with pytest.raises(thin.ThinError):
             ctx.run(t, 0, 0)
     assert np.array_equal(t.cpu().numpy(), F)
+
+
+def test_graph_mode_matches_oracle():
+    """Chunks of rounds replayed as HIP graphs: same bytes, passes and lowerings."""
+    cases = [(synth.blobs_128().image(), 0, 0), (synth.ridges_512().image()[:200, :300].copy(), 20, 0),
+             (synth.gen_blobs(150, 201, 77, np.uint16, nblobs=10, sigma=(3.0, 20.0)), 500, 1)]
+    with thin.Context(graph=True) as ctx:
+        for rep in range(2):  # the second pass replays cached graphs
+            for F, lam, adj in cases:
+                say("case graph", F.shape, lam, adj, "rep", rep)
+                t = torch.from_numpy(F.copy()).cuda()
+                st = ctx.run(t, lam, adj)
+                torch.cuda.synchronize()
+                assert_same(F, lam, adj, t.cpu().numpy(), st)
+        Fs = [synth.gen_blobs(64 + 37 * i, 90 + 23 * i, 300 + i) for i in range(12)]
+        ts = [torch.from_numpy(F.copy()).cuda() for F in Fs]
+        sts = ctx.run_batch(ts, [5] * 12, [0] * 12)
+        for F, t, st in zip(Fs, ts, sts):
+            assert_same(F, 5, 0, t.cpu().numpy(), st)
+
+
+def test_autotune_leaves_inputs_and_results_unchanged():
+    Fs = [synth.gen_blobs(80 + 40 * i, 120 + 30 * i, 500 + i, np.uint16 if i % 2 else np.uint8)
+          for i in range(6)]
+    lams = [0, 5, 20, 50, 0, 300]
+    adjs = [0, 1, 0, 1, 0, 1]
+    ts = [torch.from_numpy(F.copy()).cuda() for F in Fs]
+    say("case autotune")
+    with thin.Context() as ctx:
+        res = ctx.autotune(ts, lams, adjs, reps=2)
+        torch.cuda.synchronize()
+        for F, t in zip(Fs, ts):
+            assert np.array_equal(t.cpu().numpy(), F)
+        assert res["candidates"] > 1 and res["ms"] > 0 and res["default_ms"] > 0
+        assert res["steps_per_round"] in (8, 16, 32) and res["threads"] in (256, 512, 1024)
+        sts = ctx.run_batch(ts, lams, adjs)
+    for F, t, st, lam, adj in zip(Fs, ts, sts, lams, adjs):
+        assert_same(F, lam, adj, t.cpu().numpy(), st)
