@@ -88,7 +88,9 @@ typedef struct thin_config {
     int32_t tile;               /* tile side in pixels for the tiled engine; 0 = automatic */
     int32_t steps_per_round;    /* parity steps per tile residency (halo width); 0 = automatic */
     uint32_t flags;             /* THIN_FLAG_* */
-    uint32_t reserved;
+    int32_t threads;            /* with tile: threads per tile, 0 = first compiled choice */
+    int32_t variant;            /* with tile and threads: residency variant (thin_tune_result) */
+    int32_t reserved;
 } thin_config;
 
 /* thin_config.flags */

@@ -93,10 +93,13 @@ hipError_t launch_init_state(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t*
                              int ntiles, int32_t* hist_round, WorkList wl);
 // The launch's round is `round`, plus *round_base when round_base is not
 // null (graph replays: the same launches serve every chunk of rounds).
+// Launch flags of the round kernels.
+constexpr int kOneImage = 1;     // every tile belongs to image 0 (no tile_img lookup)
+constexpr int kStateIsTile = 2;  // a tile's state index is its tile index
 hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                         const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
                         const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
-                        int32_t* hist_round, WorkList wl, const int32_t* round_base);
+                        int32_t* hist_round, WorkList wl, const int32_t* round_base, int kflags);
 // *round_base += n (the last node of a chunk graph).
 hipError_t launch_advance(hipStream_t stream, int32_t* round_base, int n);
 // Words of one tile's change bitmap (two copies of ntiles bitmaps are needed).
@@ -108,7 +111,8 @@ hipError_t launch_step(hipStream_t stream, const ImgDev* img_host, const ImgDev*
 hipError_t launch_coop(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                        const int32_t* tile_img, int32_t* tile_last, int ntiles,
                        const TopoEntry* lut, int32_t* active, int32_t* rounds_out,
-                       int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round);
+                       int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round,
+                       int kflags);
 bool tile_shape_supported(TileShape s);
 // Every compiled shape: writes up to cap of them to out, returns the count.
 int compiled_shapes(TileShape* out, int cap);

@@ -290,20 +290,76 @@ __device__ __forceinline__ void store_wide(const View& d, P* dst, int gy0, int g
     }
 }
 
-// Interior copy src -> dst in groups of 4.
-template <typename P, int TH, int TW, int NT>
-__device__ __forceinline__ void copy_wide(const View& d, const P* src, P* dst, int gy0, int gx0,
-                                          int tid)
+// Region rows [0, RH) x columns [0, RW) of src, origin (ry0, rx0), into
+// s_img at (y + OY, x + OX) with row pitch RWP, one pixel per load, up to
+// STAGE_CHUNK loads in flight per thread (more would cost registers that
+// the steps need); zeros outside the image.
+template <int RH, int RW, int RWP, int OY, int OX, int NT>
+__device__ __forceinline__ void stage_scalar(const View& d, const void* src, int ry0, int rx0,
+                                             uint16_t* s_img, int tid)
 {
-    constexpr int GW = TW / 4;
-    const int ih = min(TH, d.h - gy0), iw = min(TW, d.w - gx0);
-    for (int g = tid; g < TH * GW; g += NT) {
-        const int y = g / GW, x = 4 * (g - (g / GW) * GW);
-        if (y < ih && x < iw) {
-            const int64_t o = (int64_t)(gy0 + y) * d.pitch + gx0 + x;
-            if (x + 4 <= iw) store4(dst + o, load4(src + o));
-            else store_partial(dst + o, load_partial(src + o, iw - x), iw - x);
+    constexpr int ITER = (RH * RW + NT - 1) / NT;
+    constexpr int CH = ITER < STAGE_CHUNK ? ITER : STAGE_CHUNK;
+#pragma unroll 1
+    for (int k0 = 0; k0 < ITER; k0 += CH) {
+        uint32_t vals[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int idx = tid + (k0 + c) * NT;
+            const int y = idx / RW, x = idx - y * RW;
+            const int gi = ry0 + y, gj = rx0 + x;
+            vals[c] = 0;
+            if (idx < RH * RW && gi >= 0 && gi < d.h && gj >= 0 && gj < d.w)
+                vals[c] = load_px(src, d.dtype, (int64_t)gi * d.pitch + gj);
         }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int idx = tid + (k0 + c) * NT;
+            const int y = idx / RW, x = idx - y * RW;
+            if (idx < RH * RW) s_img[(y + OY) * RWP + x + OX] = (uint16_t)vals[c];
+        }
+    }
+}
+
+// Staging with groups of 4 pixels where the buffers allow it.
+template <int RH, int RW, int RWP, int NT>
+__device__ __forceinline__ void stage_region(const View& d, const void* src, const void* dst,
+                                             int ry0, int rx0, uint16_t* s_img, int tid)
+{
+    if (wide_ok(d, src, dst)) {
+        if (d.dtype == 1)
+            stage_wide<uint8_t, RH, RW, RWP, NT>(d, static_cast<const uint8_t*>(src), ry0, rx0,
+                                                 s_img, tid);
+        else
+            stage_wide<uint16_t, RH, RW, RWP, NT>(d, static_cast<const uint16_t*>(src), ry0, rx0,
+                                                  s_img, tid);
+    } else {
+        stage_scalar<RH, RW, RWP, 0, 0, NT>(d, src, ry0, rx0, s_img, tid);
+    }
+}
+
+// Interior of the staged region (origin (OY, OX) in s_img) to dst.
+template <int TH, int TW, int RWP, int OY, int OX, int NT>
+__device__ __forceinline__ void store_region(const View& d, const void* src, void* dst, int gy0,
+                                             int gx0, const uint16_t* s_img, int tid)
+{
+    if constexpr (OX % 4 == 0 && RWP % 4 == 0 && TW % 4 == 0) {
+        if (wide_ok(d, src, dst)) {
+            if (d.dtype == 1)
+                store_wide<uint8_t, TH, TW, RWP, OY, OX, NT>(d, static_cast<uint8_t*>(dst), gy0,
+                                                             gx0, s_img, tid);
+            else
+                store_wide<uint16_t, TH, TW, RWP, OY, OX, NT>(d, static_cast<uint16_t*>(dst), gy0,
+                                                              gx0, s_img, tid);
+            return;
+        }
+    }
+    const int ih = min(TH, d.h - gy0), iw = min(TW, d.w - gx0);
+    for (int idx = tid; idx < TH * TW; idx += NT) {
+        const int y = idx / TW, x = idx - y * TW;
+        if (y < ih && x < iw)
+            store_px(dst, d.dtype, (int64_t)(gy0 + y) * d.pitch + (gx0 + x),
+                     s_img[(OY + y) * RWP + (OX + x)]);
     }
 }
 
@@ -360,22 +416,23 @@ struct Tile {
     static_assert(!SEED || 2 * K <= TH, "history seeding needs the region inside the 3x3 tile block");
     static_assert(TH % 2 == 0 && TW % 2 == 0 && K % 2 == 0, "tile sides and halo must be even");
 
-    // Interior copy src -> dst (a stable tile keeping the ping-pong pair equal).
-    static __device__ void copy_interior(const View d, int gy0, int gx0, const void* src,
-                                         void* dst, int tid)
+
+    // Tile and halo from src into s_img (no barrier).
+    static __device__ __forceinline__ void stage(const View& d, int gy0, int gx0, const void* src,
+                                                 const void* dst, uint16_t* s_img, int tid)
     {
-        const int ih = min(TH, d.h - gy0), iw = min(TW, d.w - gx0);
-        for (int idx = tid; idx < TH * TW; idx += NT) {
-            const int y = idx / TW, x = idx - y * TW;
-            if (y < ih && x < iw) {
-                const int64_t o = (int64_t)(gy0 + y) * d.pitch + (gx0 + x);
-                store_px(dst, d.dtype, o, load_px(src, d.dtype, o));
-            }
-        }
+        stage_region<RH, RW, RWP, NT>(d, src, dst, gy0 - K, gx0 - K, s_img, tid);
     }
 
-    // Stages the tile and its halo from src, runs nsteps parity steps starting
-    // at image step t0, writes the interior to dst.  Returns the number of
+    // Interior of the staged tile to dst.
+    static __device__ __forceinline__ void store(const View& d, int gy0, int gx0, const void* src,
+                                                 void* dst, const uint16_t* s_img, int tid)
+    {
+        store_region<TH, TW, RWP, K, K, NT>(d, src, dst, gy0, gx0, s_img, tid);
+    }
+
+    // Runs nsteps parity steps on the tile staged by stage() (followed by a
+    // barrier), starting at image step t0, and writes the interior to dst.  Returns the number of
     // interior lowerings (same value in every thread) and, in last_tau
     // (block-uniform), the last step index within the residency that lowered
     // an interior pixel (-1 if none).  Must be entered by all NT threads after
@@ -412,35 +469,9 @@ struct Tile {
         }
         if constexpr (SEED)
             for (int i = tid; i < TH * WPR; i += NT) s_bits[i] = 0u;
-        // All global loads of the region are issued before the first one is
-        // waited for.  Zeros outside the image are never read by a candidate:
-        // every candidate is an interior pixel whose 3x3 lies inside the image.
-        // Loads are issued in chunks of up to STAGE_CHUNK per thread before
-        // the first is waited for (more in flight would cost registers that
-        // the steps need).
-        constexpr int ITER = (RH * RW + NT - 1) / NT;
-        constexpr int CH = ITER < STAGE_CHUNK ? ITER : STAGE_CHUNK;
-#pragma unroll 1
-        for (int k0 = 0; k0 < ITER; k0 += CH) {
-            uint32_t vals[CH];
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int idx = tid + (k0 + c) * NT;
-                const int y = idx / RW, x = idx - y * RW;
-                const int gi = ry0 + y, gj = rx0 + x;
-                vals[c] = 0;
-                if (idx < RH * RW && gi >= 0 && gi < d.h && gj >= 0 && gj < d.w)
-                    vals[c] = load_px(src, d.dtype, (int64_t)gi * d.pitch + gj);
-            }
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int idx = tid + (k0 + c) * NT;
-                const int y = idx / RW, x = idx - y * RW;
-                if (idx < RH * RW) {
-                    s_img[y * RWP + x] = (uint16_t)vals[c];
-                    s_dirty[y * RWP + x] = seeded ? 0 : 1;
-                }
-            }
+        if (!seeded) {
+            uint32_t* f = reinterpret_cast<uint32_t*>(s_dirty);
+            for (int i = tid; i < RH * RWP / 4; i += NT) f[i] = 0x01010101u;
         }
         __syncthreads();
         if constexpr (SEED) if (seeded) {
@@ -535,13 +566,7 @@ struct Tile {
             __syncthreads();
         }
 
-        const int ih = min(TH, d.h - gy0), iw = min(TW, d.w - gx0);
-        for (int idx = tid; idx < TH * TW; idx += NT) {
-            const int y = idx / TW, x = idx - y * TW;
-            if (y < ih && x < iw)
-                store_px(dst, d.dtype, (int64_t)(gy0 + y) * d.pitch + (gx0 + x),
-                         s_img[(K + y) * RWP + (K + x)]);
-        }
+        store(d, gy0, gx0, src, dst, s_img, tid);
         if (my_count) atomicAdd(s_count, my_count);
         __syncthreads();
         if constexpr (SEED) {
@@ -596,10 +621,27 @@ struct RTile {
         return m;
     }
 
-    static __device__ void copy_interior(const View d, int gy0, int gx0, const void* src,
-                                         void* dst, int tid)
+
+    // Tile and halo from src into s_img, spare rows and columns zeroed (they
+    // are read into windows but never used by a candidate); no barrier.
+    static __device__ __forceinline__ void stage(const View& d, int gy0, int gx0, const void* src,
+                                                 const void*, uint16_t* s_img, int tid)
     {
-        Tile<TH, TW, K, NT, false>::copy_interior(d, gy0, gx0, src, dst, tid);
+        for (int i = tid; i < 2 * RWP + 2 * RH; i += NT) {
+            int o;
+            if (i < RWP) o = i;
+            else if (i < 2 * RWP) o = (RH + 1) * RWP + (i - RWP);
+            else if (i < 2 * RWP + RH) o = (i - 2 * RWP + 1) * RWP;
+            else o = (i - 2 * RWP - RH + 1) * RWP + RWP - 1;
+            s_img[o] = 0;
+        }
+        stage_scalar<RH, RW, RWP, 1, 1, NT>(d, src, gy0 - K, gx0 - K, s_img, tid);
+    }
+
+    static __device__ __forceinline__ void store(const View& d, int gy0, int gx0, const void* src,
+                                                 void* dst, const uint16_t* s_img, int tid)
+    {
+        store_region<TH, TW, RWP, K + 1, K + 1, NT>(d, src, dst, gy0, gx0, s_img, tid);
     }
 
     struct Cells {
@@ -691,38 +733,8 @@ struct RTile {
             *s_count = 0;
             *s_last = -1;
         }
-        constexpr int ITER = (RH * RW + NT - 1) / NT;
-        constexpr int CH = ITER < STAGE_CHUNK ? ITER : STAGE_CHUNK;
-        // spare rows and columns (read into windows, never used by a candidate)
-        for (int i = tid; i < 2 * RWP + 2 * RH; i += NT) {
-            int o;
-            if (i < RWP) o = i;
-            else if (i < 2 * RWP) o = (RH + 1) * RWP + (i - RWP);
-            else if (i < 2 * RWP + RH) o = (i - 2 * RWP + 1) * RWP;
-            else o = (i - 2 * RWP - RH + 1) * RWP + RWP - 1;
-            s_img[o] = 0;
-        }
-#pragma unroll 1
-        for (int k0 = 0; k0 < ITER; k0 += CH) {
-            uint32_t vals[CH];
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int idx = tid + (k0 + c) * NT;
-                const int y = idx / RW, x = idx - y * RW;
-                const int gi = ry0 + y, gj = rx0 + x;
-                vals[c] = 0;
-                if (idx < RH * RW && gi >= 0 && gi < d.h && gj >= 0 && gj < d.w)
-                    vals[c] = load_px(src, d.dtype, (int64_t)gi * d.pitch + gj);
-            }
-#pragma unroll
-            for (int c = 0; c < CH; ++c) {
-                const int idx = tid + (k0 + c) * NT;
-                const int y = idx / RW, x = idx - y * RW;
-                if (idx < RH * RW) s_img[at(y, x)] = (uint16_t)vals[c];
-            }
-        }
-        __syncthreads();
-
+        // The barrier after the windows are read also orders the counter
+        // reset above before the steps' updates.
         Cells q;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
@@ -743,6 +755,7 @@ struct RTile {
                 q.win[k][4 * i + 3] = w1 >> 16;
             }
         }
+        __syncthreads();
 
         int my_count = 0;
         for (int tau = 0; tau < nsteps; tau += 4) {
@@ -752,13 +765,7 @@ struct RTile {
             if (tau + 3 < nsteps) full_step<3>(q, d, ry0, rx0, s_img, tau + 3, lut, s_last, tid, my_count);
         }
 
-        const int ih = min(TH, d.h - gy0), iw = min(TW, d.w - gx0);
-        for (int idx = tid; idx < TH * TW; idx += NT) {
-            const int y = idx / TW, x = idx - y * TW;
-            if (y < ih && x < iw)
-                store_px(dst, d.dtype, (int64_t)(gy0 + y) * d.pitch + (gx0 + x),
-                         s_img[at(K + y, K + x)]);
-        }
+        store(d, gy0, gx0, src, dst, s_img, tid);
         if (my_count) atomicAdd(s_count, my_count);
         __syncthreads();
         last_tau = *s_last;
@@ -805,17 +812,17 @@ struct BTile {
     static_assert(!SEED || TW % 32 == 0, "history bitmaps need a tile width multiple of 32");
     static_assert(!SEED || 2 * K <= TH, "history seeding needs the region inside the 3x3 tile block");
 
-    static __device__ void copy_interior(const View d, int gy0, int gx0, const void* src,
-                                         void* dst, int tid)
+
+    static __device__ __forceinline__ void stage(const View& d, int gy0, int gx0, const void* src,
+                                                 const void* dst, uint16_t* s_img, int tid)
     {
-        if (!wide_ok(d, src, dst))
-            Tile<TH, TW, K, NT, false>::copy_interior(d, gy0, gx0, src, dst, tid);
-        else if (d.dtype == 1)
-            copy_wide<uint8_t, TH, TW, NT>(d, static_cast<const uint8_t*>(src),
-                                           static_cast<uint8_t*>(dst), gy0, gx0, tid);
-        else
-            copy_wide<uint16_t, TH, TW, NT>(d, static_cast<const uint16_t*>(src),
-                                            static_cast<uint16_t*>(dst), gy0, gx0, tid);
+        stage_region<RH, RW, RWP, NT>(d, src, dst, gy0 - K, gx0 - K, s_img, tid);
+    }
+
+    static __device__ __forceinline__ void store(const View& d, int gy0, int gx0, const void* src,
+                                                 void* dst, const uint16_t* s_img, int tid)
+    {
+        store_region<TH, TW, RWP, K, K, NT>(d, src, dst, gy0, gx0, s_img, tid);
     }
 
     // Bits of lattice word j that exist (cells b < LAT_W).
@@ -855,36 +862,6 @@ struct BTile {
         }
         if constexpr (SEED)
             for (int i = tid; i < TH * WPR; i += NT) s_bits[i] = 0u;
-        const bool wide = wide_ok(d, src, dst);
-        if (wide && d.dtype == 1) {
-            stage_wide<uint8_t, RH, RW, RWP, NT>(d, static_cast<const uint8_t*>(src), ry0, rx0,
-                                                 s_img, tid);
-        } else if (wide) {
-            stage_wide<uint16_t, RH, RW, RWP, NT>(d, static_cast<const uint16_t*>(src), ry0, rx0,
-                                                  s_img, tid);
-        } else {
-            constexpr int ITER = (RH * RW + NT - 1) / NT;
-            constexpr int CH = ITER < STAGE_CHUNK ? ITER : STAGE_CHUNK;
-#pragma unroll 1
-            for (int k0 = 0; k0 < ITER; k0 += CH) {
-                uint32_t vals[CH];
-#pragma unroll
-                for (int c = 0; c < CH; ++c) {
-                    const int idx = tid + (k0 + c) * NT;
-                    const int y = idx / RW, x = idx - y * RW;
-                    const int gi = ry0 + y, gj = rx0 + x;
-                    vals[c] = 0;
-                    if (idx < RH * RW && gi >= 0 && gi < d.h && gj >= 0 && gj < d.w)
-                        vals[c] = load_px(src, d.dtype, (int64_t)gi * d.pitch + gj);
-                }
-#pragma unroll
-                for (int c = 0; c < CH; ++c) {
-                    const int idx = tid + (k0 + c) * NT;
-                    const int y = idx / RW, x = idx - y * RW;
-                    if (idx < RH * RW) s_img[y * RWP + x] = (uint16_t)vals[c];
-                }
-            }
-        }
         if (!seeded) {
             for (int i = tid; i < 4 * CLASS_WORDS; i += NT) s_db[i] = valid_bits(i % LWW);
         } else if constexpr (SEED) {
@@ -1024,21 +1001,7 @@ struct BTile {
             __syncthreads();
         }
 
-        if (wide && d.dtype == 1) {
-            store_wide<uint8_t, TH, TW, RWP, K, K, NT>(d, static_cast<uint8_t*>(dst), gy0, gx0,
-                                                       s_img, tid);
-        } else if (wide) {
-            store_wide<uint16_t, TH, TW, RWP, K, K, NT>(d, static_cast<uint16_t*>(dst), gy0, gx0,
-                                                        s_img, tid);
-        } else {
-            const int ih = min(TH, d.h - gy0), iw = min(TW, d.w - gx0);
-            for (int idx = tid; idx < TH * TW; idx += NT) {
-                const int y = idx / TW, x = idx - y * TW;
-                if (y < ih && x < iw)
-                    store_px(dst, d.dtype, (int64_t)(gy0 + y) * d.pitch + (gx0 + x),
-                             s_img[(K + y) * RWP + (K + x)]);
-            }
-        }
+        store(d, gy0, gx0, src, dst, s_img, tid);
         if (my_count) atomicAdd(s_count, my_count);
         __syncthreads();
         if constexpr (SEED) {
@@ -1080,11 +1043,11 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
                           int round, int ntiles, uint32_t* hist_bits, int32_t* hist_round,
                           uint16_t* s_img, uint8_t* s_dirty, uint32_t* s_bits, uint32_t* s_cw,
                           const TopoEntry* s_lut, int* s_count, int* s_last,
-                          const WorkList& wl)
+                          const WorkList& wl, int kflags)
 {
     using T = TileOf<TH, TW, K, NT, VAR>;
     const int tid = threadIdx.x;
-    const int ii = tile_img[g];
+    const int ii = (kflags & kOneImage) ? 0 : tile_img[g];
     const ImgDev* d = imgs + ii;
     const int r = round - d->round0;
     if (r < 0) return 0;
@@ -1094,35 +1057,37 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
     const int lt = g - d->tile0;
     const int ty = lt / d->tiles_x, tx = lt - ty * d->tiles_x;
     const int slot = d->slot;
-    int32_t* st = tile_state + 2 * (d->state0 + lt);  // this tile's state pair
+    // this tile's state pair
+    int32_t* st = tile_state + 2 * ((kflags & kStateIsTile) ? (int64_t)g : d->state0 + lt);
 
     // tile_state[2g] is the latest round for which a tile of g's 3x3 tile
     // neighbourhood asked g to be active (it lowered something during the
     // last 4 steps of the round before); tile_state[2g + 1] is the last round
     // in which g itself lowered something.  Neighbours of this round may raise
     // tile_state[2g] to r + 1 while it is read here (only adding work), so one
-    // thread decides and the barrier broadcasts a block-uniform answer; the
-    // barrier also orders this tile's LDS writes after the previous tile's
-    // readers.
-    int vote = 0;
+    // thread decides and the barrier broadcasts a block-uniform answer.  The
+    // tile is staged before the answer is known, so its loads overlap the
+    // state read; the barrier also completes the staging and orders it after
+    // the previous tile's readers of LDS.
+    int act = 0, chg = 0;
     if (tid == 0) {
-        const int act = __hip_atomic_load(&st[0], __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-        const int chg = __hip_atomic_load(&st[1], __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-        vote = (r == 0 || act >= r) ? 1 : (chg == r - 1 ? 2 : 0);
+        act = __hip_atomic_load(&st[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        chg = __hip_atomic_load(&st[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    const int decision = __syncthreads_or(vote == 1) ? 1 : (__syncthreads_or(vote == 2) ? 2 : 0);
-    const bool active = decision == 1;
     const void* src = round_src(d, r);
     void* dst = round_dst(d, r);
     const int gy0 = ty * TH, gx0 = tx * TW;
     const View v = view_of(d);
-
-    if (!active) {
+    T::stage(v, gy0, gx0, src, dst, s_img, tid);
+    const int vote = tid == 0 ? ((r == 0 || act >= r) ? 1 : (chg == r - 1 ? 2 : 0)) : 0;
+    const int decision = __syncthreads_or(vote == 1) ? 1 : (__syncthreads_or(vote == 2) ? 2 : 0);
+    if (decision != 1) {
         // Stable for this round.  The output buffer already equals the input
         // unless the tile changed during the previous round.
-        if (decision == 2) T::copy_interior(v, gy0, gx0, src, dst, tid);
+        if (decision == 2) {
+            T::store(v, gy0, gx0, src, dst, s_img, tid);
+            __syncthreads();  // the next tile's staging overwrites s_img
+        }
         return 0;
     }
     Seed sd{};
@@ -1176,7 +1141,8 @@ __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, I
                                               int32_t* tile_last, int ntiles, int round,
                                               const TopoEntry* __restrict__ lut_g,
                                               uint32_t* hist_bits, int32_t* hist_round,
-                                              WorkList wl, const int32_t* round_base)
+                                              WorkList wl, const int32_t* round_base,
+                                              int kflags)
 {
     using T = TileOf<TH, TW, K, NT, VAR>;
     if (round_base != nullptr) round += *round_base;
@@ -1194,7 +1160,7 @@ __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, I
     for (int i = blockIdx.x; i < n; i += gridDim.x)
         round_tile<TH, TW, K, NT, VAR>(imgs, cnt, tile_img, tile_last, all ? i : mine[i], round,
                                        ntiles, hist_bits, hist_round, s_img, s_dirty, s_bits,
-                                       s_cw, s_lut, &s_count, &s_last, wl);
+                                       s_cw, s_lut, &s_count, &s_last, wl, kflags);
 }
 
 // ------------------------------------------------------------------ k_coop
@@ -1214,7 +1180,7 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
                                              int32_t* tile_last, int ntiles,
                                              const TopoEntry* __restrict__ lut_g, int32_t* active,
                                              int32_t* rounds_out, int max_rounds,
-                                             uint32_t* hist_bits, int32_t* hist_round)
+                                             uint32_t* hist_bits, int32_t* hist_round, int kflags)
 {
     using T = TileOf<TH, TW, K, NT, VAR>;
     __shared__ __align__(16) uint16_t s_img[T::IMG_ELEMS];
@@ -1235,7 +1201,7 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
         for (int g = blockIdx.x; g < ntiles; g += gridDim.x)
             mine += round_tile<TH, TW, K, NT, VAR>(imgs, cnt, tile_img, tile_last, g, round, ntiles,
                                               hist_bits, hist_round, s_img, s_dirty, s_bits, s_cw,
-                                              s_lut, &s_count, &s_last, WorkList{});
+                                              s_lut, &s_count, &s_last, WorkList{}, kflags);
         if (tid == 0 && mine) atomicAdd(&active[round % 3], mine);
         // Stores of every wave must be acknowledged before the grid barrier
         // publishes them.
@@ -1252,7 +1218,8 @@ template <int TH, int TW, int K, int NT, int VAR>
 hipError_t launch_coop_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                          const int32_t* tile_img, int32_t* tile_last, int ntiles,
                          const TopoEntry* lut, int32_t* active, int32_t* rounds_out,
-                         int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round)
+                         int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round,
+                         int kflags)
 {
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -1263,7 +1230,7 @@ hipError_t launch_coop_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
     void* args[] = {(void*)&imgs,       (void*)&cnt,       (void*)&tile_img,
                     (void*)&tile_last,  (void*)&ntiles,    (void*)&lut,
                     (void*)&active,     (void*)&rounds_out, (void*)&max_rounds,
-                    (void*)&hist_bits,  (void*)&hist_round};
+                    (void*)&hist_bits,  (void*)&hist_round, (void*)&kflags};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT, VAR>),
                                       dim3(grid), dim3(NT), args, 0, stream);
 }
@@ -1272,12 +1239,12 @@ template <int TH, int TW, int K, int NT, int VAR>
 hipError_t launch_round_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                           const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
                           const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
-                          int32_t* hist_round, WorkList wl, const int32_t* round_base)
+                          int32_t* hist_round, WorkList wl, const int32_t* round_base, int kflags)
 {
     const int grid = max(1, min(ntiles, grid_blocks));
     hipLaunchKernelGGL((k_round<TH, TW, K, NT, VAR>), dim3(grid), dim3(NT), 0, stream, imgs, cnt,
                        tile_img, tile_last, ntiles, round, lut, hist_bits, hist_round, wl,
-                       round_base);
+                       round_base, kflags);
     return hipGetLastError();
 }
 
@@ -1349,6 +1316,10 @@ hipError_t launch_step(hipStream_t stream, const ImgDev* img_host, const ImgDev*
     X(64, 64, 16, 512, 2)   \
     X(32, 32, 16, 512, 2)   \
     X(16, 16, 8, 256, 2)    \
+    X(16, 16, 16, 576, 2)   \
+    X(16, 16, 16, 256, 2)   \
+    X(24, 24, 12, 576, 2)   \
+    X(16, 16, 16, 576, 0)   \
     X(32, 32, 8, 256, 2)    \
     X(32, 32, 16, 256, 2)   \
     X(32, 32, 16, 1024, 2)  \
@@ -1412,13 +1383,13 @@ int round_blocks_per_cu(TileShape s)
 hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                         const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
                         const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
-                        int32_t* hist_round, WorkList wl, const int32_t* round_base)
+                        int32_t* hist_round, WorkList wl, const int32_t* round_base, int kflags)
 {
 #define X(a, b, c, n, e)                                                                    \
     if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.var == e)  \
         return launch_round_t<a, b, c, n, e>(stream, imgs, cnt, tile_img, tile_last, ntiles, \
                                              round, lut, grid_blocks, hist_bits, hist_round, wl, \
-                                             round_base);
+                                             round_base, kflags);
     THIN_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
@@ -1427,13 +1398,14 @@ hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs,
 hipError_t launch_coop(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                        const int32_t* tile_img, int32_t* tile_last, int ntiles,
                        const TopoEntry* lut, int32_t* active, int32_t* rounds_out,
-                       int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round)
+                       int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round,
+                       int kflags)
 {
 #define X(a, b, c, n, e)                                                                    \
     if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.var == e)  \
         return launch_coop_t<a, b, c, n, e>(stream, imgs, cnt, tile_img, tile_last, ntiles,  \
                                             lut, active, rounds_out, max_rounds, num_cus,    \
-                                            hist_bits, hist_round);
+                                            hist_bits, hist_round, kflags);
     THIN_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;

@@ -227,7 +227,7 @@ int ensure_snap(thin_ctx* ctx, size_t n)
 // Launches one round, bracketed by timing events when profiling.
 int timed_round(thin_ctx* ctx, size_t& ev_used, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                 const int32_t* tile_img, int32_t* tile_last, int ntiles, int round, int grid,
-                uint32_t* hist_bits, int32_t* hist_round, thin::WorkList wl)
+                uint32_t* hist_bits, int32_t* hist_round, thin::WorkList wl, int kflags)
 {
     if (ctx->profile) {
         while (ctx->prof_ev.size() < ev_used + 2) {
@@ -238,7 +238,8 @@ int timed_round(thin_ctx* ctx, size_t& ev_used, TileShape shape, const ImgDev* i
         HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used], ctx->stream));
     }
     HIP_TRY(ctx, thin::launch_round(ctx->stream, shape, imgs, cnt, tile_img, tile_last, ntiles,
-                                    round, ctx->d_lut, grid, hist_bits, hist_round, wl, nullptr));
+                                    round, ctx->d_lut, grid, hist_bits, hist_round, wl, nullptr,
+                                    kflags));
     if (ctx->profile) {
         HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used + 1], ctx->stream));
         ev_used += 2;
@@ -475,6 +476,7 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
         }
         return true;
     };
+    const int kflags = thin::kStateIsTile | (nimg == 1 ? thin::kOneImage : 0);
     // Graph mode: a chunk of rounds is one graph replay; the launches read
     // their round from a device counter that the graph's last node advances.
     const bool use_graph = ctx->graph && !ctx->profile;
@@ -484,7 +486,8 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
         for (int k = 0; k < count; ++k) {
             const hipError_t e = thin::launch_round(st, shape, d_imgs, d_cnt, d_tile_img,
                                                     d_tile_last, ntiles, k, ctx->d_lut, grid,
-                                                    d_hist_bits, d_hist_round, wl, d_round);
+                                                    d_hist_bits, d_hist_round, wl, d_round,
+                                                    kflags);
             if (e != hipSuccess) return e;
         }
         return thin::launch_advance(st, d_round, count);
@@ -513,7 +516,8 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
         } else {
             for (int k = 0; k < n; ++k) {
                 if ((rc = timed_round(ctx, ev_used, shape, d_imgs, d_cnt, d_tile_img, d_tile_last,
-                                      ntiles, launched, grid, d_hist_bits, d_hist_round, wl)))
+                                      ntiles, launched, grid, d_hist_bits, d_hist_round, wl,
+                                      kflags)))
                     return rc;
                 ++launched;
             }
@@ -655,7 +659,8 @@ int run_coop(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
     HIP_TRY(ctx, thin::launch_coop(ctx->stream, shape, d_imgs, d_cnt, d_tile_img, d_tile_last,
                                    ntiles, ctx->d_lut, d_small, d_small + 3, rounds_cap,
                                    ctx->num_cus, static_cast<uint32_t*>(ctx->hist_bits.ptr),
-                                   static_cast<int32_t*>(ctx->hist_round.ptr)));
+                                   static_cast<int32_t*>(ctx->hist_round.ptr),
+                                   thin::kStateIsTile | (nimg == 1 ? thin::kOneImage : 0)));
     if (ctx->profile) {
         HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[1], ctx->stream));
         ev_used = 2;
@@ -910,7 +915,10 @@ int thin_create(thin_ctx** out, const thin_config* cfg)
     if (c.engine < 0 || c.engine > THIN_ENGINE_COOP) return THIN_EINVAL;
     if ((c.tile != 0) != (c.steps_per_round != 0)) return THIN_EINVAL;
     TileShape forced{0, 0, 0, 0, 0};
-    if (c.tile) {
+    if (c.tile && c.threads) {
+        forced = TileShape{c.tile, c.tile, c.steps_per_round, c.threads, c.variant};
+        if (!thin::tile_shape_supported(forced)) return THIN_EINVAL;
+    } else if (c.tile) {
         forced = thin::complete_shape(c.tile, c.tile, c.steps_per_round);
         if (!forced.nt) return THIN_EINVAL;
     }
@@ -1213,7 +1221,8 @@ int thin_serve_step(thin_ctx* ctx, int32_t rounds, uint64_t* done_tags, thin_sta
                                   d_cnt, static_cast<int32_t*>(ctx->serve_tile_img.ptr), d_state,
                                   ntiles, ctx->serve_round + k, grid,
                                   static_cast<uint32_t*>(ctx->hist_bits.ptr),
-                                  static_cast<int32_t*>(ctx->hist_round.ptr), thin::WorkList{})))
+                                  static_cast<int32_t*>(ctx->hist_round.ptr), thin::WorkList{},
+                                  0)))
                 return rc;
         }
         ctx->serve_round += rounds;

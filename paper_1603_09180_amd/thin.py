@@ -45,7 +45,9 @@ class thin_config(ctypes.Structure):
         ("tile", ctypes.c_int32),
         ("steps_per_round", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("threads", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -254,7 +256,8 @@ class Context:
 
     def __init__(self, device: int = 0, stream=None, engine: int = THIN_ENGINE_AUTO,
                  max_device_bytes: int = 0, max_passes: int = 0, tile: int = 0,
-                 steps_per_round: int = 0, profile: bool = False, graph: bool = False):
+                 steps_per_round: int = 0, profile: bool = False, graph: bool = False,
+                 threads: int = 0, variant: int = 0):
         import torch
 
         if stream is None:
@@ -267,6 +270,8 @@ class Context:
         cfg.max_passes = max_passes
         cfg.tile = tile
         cfg.steps_per_round = steps_per_round
+        cfg.threads = threads
+        cfg.variant = variant
         cfg.flags = (THIN_FLAG_PROFILE if profile else 0) | (THIN_FLAG_GRAPH if graph else 0)
         self.device = device
         self.stream = stream

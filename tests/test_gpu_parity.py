@@ -111,7 +111,8 @@ ALL_SHAPES = ["16,16,8,256,0", "32,32,8,256,0", "32,32,8,512,0", "32,32,16,256,0
               "64,64,8,512,0", "64,64,8,1024,0", "64,64,16,256,0", "64,64,16,512,0",
               "64,64,16,1024,0", "64,64,16,1024,1", "64,64,32,512,0", "64,64,32,1024,0",
               "128,128,16,512,0", "128,128,16,512,1", "64,64,16,512,1",
-              "16,16,8,256,2", "32,32,8,256,2", "32,32,16,256,2", "32,32,16,512,2",
+              "16,16,8,256,2", "16,16,16,576,2", "16,16,16,256,2", "24,24,12,576,2",
+              "16,16,16,576,0", "32,32,8,256,2", "32,32,16,256,2", "32,32,16,512,2",
               "32,32,16,1024,2", "32,32,32,1024,2", "64,64,16,512,2", "64,64,16,1024,2",
               "64,64,32,1024,2",
               "32,32,16,256,3", "32,32,16,512,3", "64,64,16,512,3", "64,64,16,512,4",
