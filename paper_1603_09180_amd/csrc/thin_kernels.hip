@@ -773,13 +773,29 @@ struct RTile {
     }
 };
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves: shifts by
+// 1, 2, 4 and 8 lanes within each row of 16, then the last lane of row 0 and
+// of row 2 broadcast into the next row, then lane 31 into rows 2 and 3.
+// Lanes a move cannot reach add the 0 kept in `old`.
+__device__ __forceinline__ int wave_inclusive_sum(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 // Residency with bit flags and dense work lists.  The re-examination flags
 // are one bit per lattice cell and parity class (4 bitmaps of LAT_H rows of
-// LWW words).  Each step takes the flagged candidates of its class inside
-// the exact region (one bitmap word per thread), clears those bits, and
-// writes the candidates into a list in LDS at offsets from a block-wide
-// prefix sum; the block then examines the list densely, so clean candidates
-// cost nothing beyond their share of one word.  A lowered pixel sets the
+// LWW words).  Each step, every wave takes the flagged candidates of its
+// class inside the exact region from its run of bitmap words (one word per
+// lane), clears those bits and writes
+// the candidates into its own list in LDS at offsets from a wave prefix sum;
+// after one barrier the block examines the concatenated lists densely, so
+// clean candidates cost nothing beyond their share of one word.  A lowered pixel sets the
 // bits of its whole 3x3 (section 2.2 re-examination rule, as in the other
 // variants).  With SEED, the initial flags of round r > 0 come from the
 // change bitmaps of round r - 1 (the pixels that tiles lowered during their
@@ -797,8 +813,15 @@ struct BTile {
     static constexpr int LWW = (LAT_W + 31) / 32;     // bitmap words per lattice row
     static constexpr int CLASS_WORDS = LAT_H * LWW;   // bitmap words per class
     static constexpr int NWAVE = NT / 64;
-    static constexpr int LIST_ELEMS = (NCELL + 1) & ~1;
-    // LDS bytes behind the flag pointer: 4 bitmaps, the list, wave totals
+    // Bitmap words of a class are dealt to the waves in runs of WAVE_WORDS
+    // (one per lane), so the wave lists, concatenated, are in raster order
+    // and neighbouring lanes examine neighbouring cells.
+    static constexpr int WAVE_ROWS = (LAT_H + NWAVE - 1) / NWAVE;  // whole lattice rows
+    static constexpr int WAVE_WORDS = WAVE_ROWS * LWW;
+    static constexpr int WAVE_CAP = WAVE_ROWS * LAT_W;              // cells of those rows
+    static constexpr int LIST_ELEMS = NWAVE * WAVE_CAP;
+    // LDS bytes behind the flag pointer: 4 bitmaps, the wave lists and the
+    // wave list lengths
     static constexpr int DIRTY_ELEMS = 16 * CLASS_WORDS + 2 * LIST_ELEMS + 4 * NWAVE;
     static constexpr int WPR = TW >= 32 ? TW / 32 : 1;
     static constexpr int RWW = (RW + 31) / 32;
@@ -808,6 +831,8 @@ struct BTile {
     static_assert(K <= TH && K <= TW, "halo must not exceed the tile side");
     static_assert(TH % 4 == 0 && TW % 4 == 0, "tile sides must be multiples of 4");
     static_assert(NT % 64 == 0 && CLASS_WORDS <= NT, "one bitmap word per thread");
+    static_assert(WAVE_WORDS <= 64, "one bitmap word per lane");
+    static_assert(LIST_ELEMS >= NCELL, "wave lists hold every cell");
     static_assert(NCELL < 65536, "list entries are 16-bit");
     static_assert(!SEED || TW % 32 == 0, "history bitmaps need a tile width multiple of 32");
     static_assert(!SEED || 2 * K <= TH, "history seeding needs the region inside the 3x3 tile block");
@@ -853,7 +878,7 @@ struct BTile {
         (void)t0;  // a multiple of 4: step tau has class tau mod 4
         uint32_t* s_db = reinterpret_cast<uint32_t*>(s_flags);           // [4][LAT_H][LWW]
         uint16_t* s_list = reinterpret_cast<uint16_t*>(s_db + 4 * CLASS_WORDS);
-        int* s_wsum = reinterpret_cast<int*>(s_list + LIST_ELEMS);
+        int* s_wlen = reinterpret_cast<int*>(s_list + LIST_ELEMS);
         const int ry0 = gy0 - K, rx0 = gx0 - K;
         const bool seeded = SEED && sd != nullptr && sd->r > 0;
         if (tid == 0) {
@@ -914,7 +939,9 @@ struct BTile {
 
         const uint32_t lambda = d.lambda;
         const int wave = tid >> 6, lane = tid & 63;
-        const int wa = tid / LWW, wj = tid - (tid / LWW) * LWW;  // this thread's bitmap word
+        const int myw = lane < WAVE_WORDS ? wave * WAVE_WORDS + lane : CLASS_WORDS;  // its word
+        const int wa = myw / LWW, wj = myw - (myw / LWW) * LWW;
+        uint16_t* my_list = s_list + wave * WAVE_CAP;
         int my_count = 0;
         for (int tau = 0; tau < nsteps; ++tau) {
             const int c = tau & 3, si = c >> 1, sj = c & 1;
@@ -925,45 +952,41 @@ struct BTile {
             const int a_lo = (r_lo - si + 1) >> 1, a_hi = (r_hi - si) >> 1;
             const int b_lo = (c_lo - sj + 1) >> 1, b_hi = (c_hi - sj) >> 1;
             uint32_t take = 0u;
-            if (tid < CLASS_WORDS && wa >= a_lo && wa <= a_hi) {
+            if (myw < CLASS_WORDS && wa >= a_lo && wa <= a_hi) {
                 const int lo = max(b_lo - 32 * wj, 0), hi = min(b_hi - 32 * wj, 31);
                 if (lo <= hi) {
                     const uint32_t mask = (hi == 31 ? ~0u : ((2u << hi) - 1u)) & ~((1u << lo) - 1u);
-                    uint32_t* p = s_db + c * CLASS_WORDS + tid;
+                    uint32_t* p = s_db + c * CLASS_WORDS + myw;
                     const uint32_t w = *p;
                     take = w & mask;
                     if (take) *p = w & ~mask;
                 }
             }
             const int cnt = __popc(take);
-            int incl = cnt;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int v = __shfl_up(incl, o);
-                if (lane >= o) incl += v;
-            }
-            if (lane == 63) s_wsum[wave] = incl;
-            __syncthreads();
-            int base = 0, total = 0;
-#pragma unroll
-            for (int wv = 0; wv < NWAVE; ++wv) {
-                const int sv = s_wsum[wv];
-                base += wv < wave ? sv : 0;
-                total += sv;
-            }
+            const int incl = wave_inclusive_sum(cnt);
+            if (lane == 63) s_wlen[wave] = incl;
             if (take) {
-                int off = base + incl - cnt;
+                int off = incl - cnt;
                 const int cell0 = wa * LAT_W + 32 * wj;
                 uint32_t t = take;
                 while (t) {
-                    s_list[off++] = (uint16_t)(cell0 + __ffs(t) - 1);
+                    my_list[off++] = (uint16_t)(cell0 + __ffs(t) - 1);
                     t &= t - 1u;
                 }
             }
             __syncthreads();
+            // The wave lists, concatenated, are examined by the whole block.
+            int start[NWAVE + 1];
+            start[0] = 0;
+#pragma unroll
+            for (int wv = 0; wv < NWAVE; ++wv) start[wv + 1] = start[wv] + s_wlen[wv];
+            const int total = start[NWAVE];
             bool inner = false;
             for (int i = tid; i < total; i += NT) {
-                const int cell = s_list[i];
+                int wv = 0;
+#pragma unroll
+                for (int q = 1; q < NWAVE; ++q) wv += i >= start[q] ? 1 : 0;
+                const int cell = s_list[wv * WAVE_CAP + i - start[wv]];
                 const int a = cell / LAT_W, b = cell - a * LAT_W;
                 const int lr = 2 * a + si, lc = 2 * b + sj;
                 uint16_t* p = s_img + lr * RWP + lc;
