@@ -96,9 +96,12 @@ hipError_t launch_init_state(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t*
 // Launch flags of the round kernels.
 constexpr int kOneImage = 1;     // every tile belongs to image 0 (no tile_img lookup)
 constexpr int kStateIsTile = 2;  // a tile's state index is its tile index
+constexpr int kOnlyU8 = 4;       // visit only u8 images (bit-flag variants: u8 LDS tiles)
+constexpr int kOnlyU16 = 8;      // visit only u16 images
+// A grid of as many blocks as fit on num_cus CUs loops over the tiles.
 hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                         const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
-                        const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
+                        const TopoEntry* lut, int num_cus, uint32_t* hist_bits,
                         int32_t* hist_round, WorkList wl, const int32_t* round_base, int kflags);
 // *round_base += n (the last node of a chunk graph).
 hipError_t launch_advance(hipStream_t stream, int32_t* round_base, int n);

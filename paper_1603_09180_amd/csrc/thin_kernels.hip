@@ -363,6 +363,109 @@ __device__ __forceinline__ void store_region(const View& d, const void* src, voi
     }
 }
 
+// Staging and store with the LDS tile in the image's own pixel type E (u8
+// tiles take half the LDS of u16 ones).  Groups of 4 pixels move unchanged
+// between global memory and LDS where the buffers allow it.
+template <typename E>
+__device__ __forceinline__ void copy4(E* dst, const E* src)
+{
+    if constexpr (sizeof(E) == 1) *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(src);
+    else *reinterpret_cast<uint2*>(dst) = *reinterpret_cast<const uint2*>(src);
+}
+
+template <typename E, int RH, int RW, int RWP, int NT>
+__device__ __forceinline__ void stage_native(const View& d, const void* srcv, const void* dstv,
+                                             int ry0, int rx0, E* s_img, int tid)
+{
+    static_assert(RW % 4 == 0 && RWP % 4 == 0, "groups of 4 pixels");
+    const E* src = static_cast<const E*>(srcv);
+    if (!wide_ok(d, srcv, dstv)) {
+        constexpr int ITER = (RH * RW + NT - 1) / NT;
+        constexpr int CH = ITER < STAGE_CHUNK ? ITER : STAGE_CHUNK;
+#pragma unroll 1
+        for (int k0 = 0; k0 < ITER; k0 += CH) {
+            E vals[CH];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int idx = tid + (k0 + c) * NT;
+                const int y = idx / RW, x = idx - y * RW;
+                const int gi = ry0 + y, gj = rx0 + x;
+                vals[c] = 0;
+                if (idx < RH * RW && gi >= 0 && gi < d.h && gj >= 0 && gj < d.w)
+                    vals[c] = src[(int64_t)gi * d.pitch + gj];
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int idx = tid + (k0 + c) * NT;
+                const int y = idx / RW, x = idx - y * RW;
+                if (idx < RH * RW) s_img[y * RWP + x] = vals[c];
+            }
+        }
+        return;
+    }
+    using V = typename std::conditional<sizeof(E) == 1, uint32_t, uint2>::type;
+    constexpr int GW = RW / 4, NG = RH * GW;
+    constexpr int ITER = (NG + NT - 1) / NT;
+    constexpr int CH = ITER < STAGE_CHUNK ? ITER : STAGE_CHUNK;
+#pragma unroll 1
+    for (int k0 = 0; k0 < ITER; k0 += CH) {
+        V v[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int g = tid + (k0 + c) * NT;
+            const int y = g / GW, x = 4 * (g - (g / GW) * GW);
+            const int gi = ry0 + y, gj = rx0 + x;
+            v[c] = V{};
+            if (g < NG && gi >= 0 && gi < d.h && gj >= 0 && gj < d.w) {
+                const E* row = src + (int64_t)gi * d.pitch + gj;
+                if (gj + 4 <= d.w) {
+                    v[c] = *reinterpret_cast<const V*>(row);
+                } else {
+                    E q[4] = {0, 0, 0, 0};
+                    for (int i = 0; i < d.w - gj; ++i) q[i] = row[i];
+                    v[c] = *reinterpret_cast<const V*>(q);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int g = tid + (k0 + c) * NT;
+            if (g < NG) {
+                const int y = g / GW, x = 4 * (g - (g / GW) * GW);
+                *reinterpret_cast<V*>(s_img + y * RWP + x) = v[c];
+            }
+        }
+    }
+}
+
+template <typename E, int TH, int TW, int RWP, int OY, int OX, int NT>
+__device__ __forceinline__ void store_native(const View& d, const void* srcv, void* dstv, int gy0,
+                                             int gx0, const E* s_img, int tid)
+{
+    static_assert(TW % 4 == 0 && OX % 4 == 0 && RWP % 4 == 0, "groups of 4 pixels");
+    E* dst = static_cast<E*>(dstv);
+    const int ih = min(TH, d.h - gy0), iw = min(TW, d.w - gx0);
+    if (!wide_ok(d, srcv, dstv)) {
+        for (int idx = tid; idx < TH * TW; idx += NT) {
+            const int y = idx / TW, x = idx - y * TW;
+            if (y < ih && x < iw)
+                dst[(int64_t)(gy0 + y) * d.pitch + (gx0 + x)] = s_img[(OY + y) * RWP + (OX + x)];
+        }
+        return;
+    }
+    constexpr int GW = TW / 4;
+    for (int g = tid; g < TH * GW; g += NT) {
+        const int y = g / GW, x = 4 * (g - (g / GW) * GW);
+        if (y < ih && x < iw) {
+            const E* s = s_img + (OY + y) * RWP + OX + x;
+            E* q = dst + (int64_t)(gy0 + y) * d.pitch + gx0 + x;
+            if (x + 4 <= iw) copy4(q, s);
+            else
+                for (int i = 0; i < iw - x; ++i) q[i] = s[i];
+        }
+    }
+}
+
 // History handed from one round to the next: for every tile processed in a
 // round, a bitmap (TH rows of TW/32 words) of the interior pixels that were
 // lowered during the last 4 steps of its residency, and the round it was
@@ -398,6 +501,7 @@ __device__ __forceinline__ uint32_t history_word_t(const Seed* sd, int gi, int a
 // staged in LDS as u16, processed by NT threads.
 template <int TH, int TW, int K, int NT, bool SEED>
 struct Tile {
+    using Elem = uint16_t;
     static constexpr int RH = TH + 2 * K;
     static constexpr int RW = TW + 2 * K;
     static constexpr int RWP = RW;  // LDS row pitch in elements
@@ -595,6 +699,7 @@ struct Tile {
 // the final interior store.
 template <int TH, int TW, int K, int NT>
 struct RTile {
+    using Elem = uint16_t;
     static constexpr int RH = TH + 2 * K;
     static constexpr int RW = TW + 2 * K;
     static constexpr int RWP = RW + 2;                // a spare column on each side
@@ -802,8 +907,9 @@ __device__ __forceinline__ int wave_inclusive_sum(int v)
 // last 4 steps), dilated by the 3x3, instead of all ones: a candidate whose
 // 3x3 saw none of those changes was examined 4 steps earlier at the same
 // values.
-template <int TH, int TW, int K, int NT, bool SEED>
+template <int TH, int TW, int K, int NT, bool SEED, typename E>
 struct BTile {
+    using Elem = E;  // LDS pixel type: the image's own
     static constexpr int RH = TH + 2 * K;
     static constexpr int RW = TW + 2 * K;
     static constexpr int RWP = RW;
@@ -839,15 +945,15 @@ struct BTile {
 
 
     static __device__ __forceinline__ void stage(const View& d, int gy0, int gx0, const void* src,
-                                                 const void* dst, uint16_t* s_img, int tid)
+                                                 const void* dst, E* s_img, int tid)
     {
-        stage_region<RH, RW, RWP, NT>(d, src, dst, gy0 - K, gx0 - K, s_img, tid);
+        stage_native<E, RH, RW, RWP, NT>(d, src, dst, gy0 - K, gx0 - K, s_img, tid);
     }
 
     static __device__ __forceinline__ void store(const View& d, int gy0, int gx0, const void* src,
-                                                 void* dst, const uint16_t* s_img, int tid)
+                                                 void* dst, const E* s_img, int tid)
     {
-        store_region<TH, TW, RWP, K, K, NT>(d, src, dst, gy0, gx0, s_img, tid);
+        store_native<E, TH, TW, RWP, K, K, NT>(d, src, dst, gy0, gx0, s_img, tid);
     }
 
     // Bits of lattice word j that exist (cells b < LAT_W).
@@ -870,7 +976,7 @@ struct BTile {
 
     // Same contract as Tile::run.
     static __device__ __forceinline__ int run(const View d, int gy0, int gx0, int t0, int nsteps,
-                                              const void* src, void* dst, uint16_t* s_img,
+                                              const void* src, void* dst, E* s_img,
                                               uint8_t* s_flags, uint32_t* s_bits, uint32_t* s_cw,
                                               const Seed* sd, const TopoEntry* lut, int* s_count,
                                               int* s_last, int tid, int& last_tau)
@@ -989,13 +1095,13 @@ struct BTile {
                 const int cell = s_list[wv * WAVE_CAP + i - start[wv]];
                 const int a = cell / LAT_W, b = cell - a * LAT_W;
                 const int lr = 2 * a + si, lc = 2 * b + sj;
-                uint16_t* p = s_img + lr * RWP + lc;
+                E* p = s_img + lr * RWP + lc;
                 const uint32_t v = p[0];
                 const uint32_t nbv[8] = {p[1], p[-RWP + 1], p[-RWP], p[-RWP - 1],
                                          p[-1], p[RWP - 1], p[RWP], p[RWP + 1]};
                 uint32_t alpha;
                 if (decide(v, nbv, lut, lambda, alpha)) {
-                    p[0] = (uint16_t)alpha;
+                    p[0] = (E)alpha;
 #pragma unroll
                     for (int dy = -1; dy <= 1; ++dy) {
                         const int y = lr + dy;
@@ -1039,11 +1145,13 @@ struct BTile {
     }
 };
 
-template <int TH, int TW, int K, int NT, int VAR>
+// Residency type of a variant; E is the LDS pixel type of the bit-flag
+// variants (the other variants keep u16).
+template <int TH, int TW, int K, int NT, int VAR, typename E = uint16_t>
 using TileOf = typename std::conditional<
     VAR == kVarRegs, RTile<TH, TW, K, NT>,
     typename std::conditional<VAR == kVarBits || VAR == kVarBitsSeeded,
-                              BTile<TH, TW, K, NT, VAR == kVarBitsSeeded>,
+                              BTile<TH, TW, K, NT, VAR == kVarBitsSeeded, E>,
                               Tile<TH, TW, K, NT, VAR == kVarSeeded>>::type>::type;
 
 // ----------------------------------------------------------------- k_round
@@ -1060,18 +1168,20 @@ __device__ __forceinline__ void enqueue(const WorkList& wl, int g, int next)
     }
 }
 
-template <int TH, int TW, int K, int NT, int VAR>
+template <int TH, int TW, int K, int NT, int VAR, typename E>
 __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                           const int32_t* __restrict__ tile_img, int32_t* tile_state, int g,
                           int round, int ntiles, uint32_t* hist_bits, int32_t* hist_round,
-                          uint16_t* s_img, uint8_t* s_dirty, uint32_t* s_bits, uint32_t* s_cw,
-                          const TopoEntry* s_lut, int* s_count, int* s_last,
+                          typename TileOf<TH, TW, K, NT, VAR, E>::Elem* s_img, uint8_t* s_dirty,
+                          uint32_t* s_bits, uint32_t* s_cw, const TopoEntry* __restrict__ lut_g,
+                          TopoEntry* s_lut, int& lut_adj, int* s_count, int* s_last,
                           const WorkList& wl, int kflags)
 {
-    using T = TileOf<TH, TW, K, NT, VAR>;
+    using T = TileOf<TH, TW, K, NT, VAR, E>;
     const int tid = threadIdx.x;
     const int ii = (kflags & kOneImage) ? 0 : tile_img[g];
     const ImgDev* d = imgs + ii;
+    if (((kflags & kOnlyU8) && d->dtype != 1) || ((kflags & kOnlyU16) && d->dtype != 2)) return 0;
     const int r = round - d->round0;
     if (r < 0) return 0;
     const int t0 = r * K;
@@ -1101,6 +1211,13 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
     void* dst = round_dst(d, r);
     const int gy0 = ty * TH, gx0 = tx * TW;
     const View v = view_of(d);
+    if (d->adj != lut_adj) {
+        // The block's table follows the image's pairing; the previous tile's
+        // readers are past its last barrier, and the decision barrier below
+        // orders these writes before this tile's steps.
+        lut_adj = d->adj;
+        for (int i = tid; i < 256; i += NT) s_lut[i] = lut_g[lut_adj * 256 + i];
+    }
     T::stage(v, gy0, gx0, src, dst, s_img, tid);
     const int vote = tid == 0 ? ((r == 0 || act >= r) ? 1 : (chg == r - 1 ? 2 : 0)) : 0;
     const int decision = __syncthreads_or(vote == 1) ? 1 : (__syncthreads_or(vote == 2) ? 2 : 0);
@@ -1128,7 +1245,7 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
     sd.g = g;
     int last_tau;
     const int count = T::run(v, gy0, gx0, t0, nsteps, src, dst, s_img, s_dirty, s_bits, s_cw,
-                             var_seeded(VAR) ? &sd : nullptr, s_lut + d->adj * 256, s_count, s_last, tid,
+                             var_seeded(VAR) ? &sd : nullptr, s_lut, s_count, s_last, tid,
                              last_tau);
     if (tid == 0) {
         atomicAdd(&cnt[slot].tile_rounds, 1ull);
@@ -1158,7 +1275,7 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
     return 1;
 }
 
-template <int TH, int TW, int K, int NT, int VAR>
+template <int TH, int TW, int K, int NT, int VAR, typename E>
 __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                                               const int32_t* __restrict__ tile_img,
                                               int32_t* tile_last, int ntiles, int round,
@@ -1167,23 +1284,24 @@ __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, I
                                               WorkList wl, const int32_t* round_base,
                                               int kflags)
 {
-    using T = TileOf<TH, TW, K, NT, VAR>;
+    using T = TileOf<TH, TW, K, NT, VAR, E>;
     if (round_base != nullptr) round += *round_base;
-    __shared__ __align__(16) uint16_t s_img[T::IMG_ELEMS];
+    __shared__ __align__(16) typename T::Elem s_img[T::IMG_ELEMS];
     __shared__ __align__(16) uint8_t s_dirty[T::DIRTY_ELEMS];
     __shared__ uint32_t s_bits[T::BITS_WORDS];
     __shared__ uint32_t s_cw[T::CW_WORDS];
-    __shared__ TopoEntry s_lut[512];
+    __shared__ TopoEntry s_lut[256];
     __shared__ int s_count, s_last;
-    for (int i = threadIdx.x; i < 512; i += NT) s_lut[i] = lut_g[i];
+    int lut_adj = -1;
     const bool all = wl.list == nullptr || round == wl.full;
     const int n = all ? ntiles : wl.count[round % 3];
     if (wl.list != nullptr && blockIdx.x == 0 && threadIdx.x == 0) wl.count[(round + 2) % 3] = 0;
     const int32_t* mine = all ? nullptr : wl.list + (round & 1) * wl.cap;
     for (int i = blockIdx.x; i < n; i += gridDim.x)
-        round_tile<TH, TW, K, NT, VAR>(imgs, cnt, tile_img, tile_last, all ? i : mine[i], round,
-                                       ntiles, hist_bits, hist_round, s_img, s_dirty, s_bits,
-                                       s_cw, s_lut, &s_count, &s_last, wl, kflags);
+        round_tile<TH, TW, K, NT, VAR, E>(imgs, cnt, tile_img, tile_last, all ? i : mine[i], round,
+                                          ntiles, hist_bits, hist_round, s_img, s_dirty, s_bits,
+                                          s_cw, lut_g, s_lut, lut_adj, &s_count, &s_last, wl,
+                                          kflags);
 }
 
 // ------------------------------------------------------------------ k_coop
@@ -1197,7 +1315,7 @@ __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, I
 // grid barrier of round r and is cleared during round r + 2, after the next
 // barrier has proved those reads complete.
 
-template <int TH, int TW, int K, int NT, int VAR>
+template <int TH, int TW, int K, int NT, int VAR, typename E>
 __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                                              const int32_t* __restrict__ tile_img,
                                              int32_t* tile_last, int ntiles,
@@ -1205,15 +1323,15 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
                                              int32_t* rounds_out, int max_rounds,
                                              uint32_t* hist_bits, int32_t* hist_round, int kflags)
 {
-    using T = TileOf<TH, TW, K, NT, VAR>;
-    __shared__ __align__(16) uint16_t s_img[T::IMG_ELEMS];
+    using T = TileOf<TH, TW, K, NT, VAR, E>;
+    __shared__ __align__(16) typename T::Elem s_img[T::IMG_ELEMS];
     __shared__ __align__(16) uint8_t s_dirty[T::DIRTY_ELEMS];
     __shared__ uint32_t s_bits[T::BITS_WORDS];
     __shared__ uint32_t s_cw[T::CW_WORDS];
-    __shared__ TopoEntry s_lut[512];
+    __shared__ TopoEntry s_lut[256];
     __shared__ int s_count, s_last;
     const int tid = threadIdx.x;
-    for (int i = tid; i < 512; i += NT) s_lut[i] = lut_g[i];
+    int lut_adj = -1;
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
     int round = 0;
     for (;; ++round) {
@@ -1222,9 +1340,10 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
                                __HIP_MEMORY_SCOPE_AGENT);
         int mine = 0;
         for (int g = blockIdx.x; g < ntiles; g += gridDim.x)
-            mine += round_tile<TH, TW, K, NT, VAR>(imgs, cnt, tile_img, tile_last, g, round, ntiles,
-                                              hist_bits, hist_round, s_img, s_dirty, s_bits, s_cw,
-                                              s_lut, &s_count, &s_last, WorkList{}, kflags);
+            mine += round_tile<TH, TW, K, NT, VAR, E>(imgs, cnt, tile_img, tile_last, g, round,
+                                                 ntiles, hist_bits, hist_round, s_img, s_dirty,
+                                                 s_bits, s_cw, lut_g, s_lut, lut_adj, &s_count,
+                                                 &s_last, WorkList{}, kflags);
         if (tid == 0 && mine) atomicAdd(&active[round % 3], mine);
         // Stores of every wave must be acknowledged before the grid barrier
         // publishes them.
@@ -1237,7 +1356,7 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
     if (blockIdx.x == 0 && tid == 0) *rounds_out = round + 1;
 }
 
-template <int TH, int TW, int K, int NT, int VAR>
+template <int TH, int TW, int K, int NT, int VAR, typename E>
 hipError_t launch_coop_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                          const int32_t* tile_img, int32_t* tile_last, int ntiles,
                          const TopoEntry* lut, int32_t* active, int32_t* rounds_out,
@@ -1246,7 +1365,7 @@ hipError_t launch_coop_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
 {
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT, VAR>), NT, 0);
+        &per_cu, reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT, VAR, E>), NT, 0);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     const int grid = max(1, min(ntiles, per_cu * num_cus));
@@ -1254,18 +1373,30 @@ hipError_t launch_coop_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                     (void*)&tile_last,  (void*)&ntiles,    (void*)&lut,
                     (void*)&active,     (void*)&rounds_out, (void*)&max_rounds,
                     (void*)&hist_bits,  (void*)&hist_round, (void*)&kflags};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT, VAR>),
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_coop<TH, TW, K, NT, VAR, E>),
                                       dim3(grid), dim3(NT), args, 0, stream);
 }
 
-template <int TH, int TW, int K, int NT, int VAR>
+template <int TH, int TW, int K, int NT, int VAR, typename E>
 hipError_t launch_round_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
                           const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
-                          const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
+                          const TopoEntry* lut, int num_cus, uint32_t* hist_bits,
                           int32_t* hist_round, WorkList wl, const int32_t* round_base, int kflags)
 {
-    const int grid = max(1, min(ntiles, grid_blocks));
-    hipLaunchKernelGGL((k_round<TH, TW, K, NT, VAR>), dim3(grid), dim3(NT), 0, stream, imgs, cnt,
+    // As many blocks as fit on the device at once (registers, LDS and thread
+    // slots of this instantiation), each looping over the tiles.
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &n, reinterpret_cast<const void*>(&k_round<TH, TW, K, NT, VAR, E>), NT, 0) !=
+                hipSuccess ||
+            n < 1)
+            n = 1;
+        per_cu = n;
+    }
+    const int grid = max(1, min(ntiles, per_cu * num_cus));
+    hipLaunchKernelGGL((k_round<TH, TW, K, NT, VAR, E>), dim3(grid), dim3(NT), 0, stream, imgs, cnt,
                        tile_img, tile_last, ntiles, round, lut, hist_bits, hist_round, wl,
                        round_base, kflags);
     return hipGetLastError();
@@ -1381,7 +1512,7 @@ TileShape complete_shape(int th, int tw, int k)
 
 static int lds_bytes(TileShape s)
 {
-    if (s.var == kVarRegs) return (s.th + 2 * s.k + 2) * (s.tw + 2 * s.k + 2) * 2 + 4096 + 64;
+    if (s.var == kVarRegs) return (s.th + 2 * s.k + 2) * (s.tw + 2 * s.k + 2) * 2 + 2048 + 64;
     const int region = (s.th + 2 * s.k) * (s.tw + 2 * s.k);
     const int hist = var_seeded(s.var)
                          ? (s.th * (s.tw / 32) + (s.th + 2 * s.k) * ((s.tw + 2 * s.k + 31) / 32)) * 4
@@ -1389,9 +1520,9 @@ static int lds_bytes(TileShape s)
     if (s.var == kVarBits || s.var == kVarBitsSeeded) {
         const int lat_h = (s.th + 2 * s.k) / 2, lat_w = (s.tw + 2 * s.k) / 2;
         const int flags = 16 * lat_h * ((lat_w + 31) / 32) + 2 * lat_h * lat_w + 64;
-        return region * 2 + flags + hist + 4096 + 64;
+        return region * 2 + flags + hist + 2048 + 64;
     }
-    return region * 3 + hist + 4096 + 64;
+    return region * 3 + hist + 2048 + 64;
 }
 
 int history_words(TileShape s) { return var_seeded(s.var) ? s.th * (s.tw / 32) : 1; }
@@ -1405,14 +1536,26 @@ int round_blocks_per_cu(TileShape s)
 
 hipError_t launch_round(hipStream_t stream, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                         const int32_t* tile_img, int32_t* tile_last, int ntiles, int round,
-                        const TopoEntry* lut, int grid_blocks, uint32_t* hist_bits,
+                        const TopoEntry* lut, int num_cus, uint32_t* hist_bits,
                         int32_t* hist_round, WorkList wl, const int32_t* round_base, int kflags)
 {
-#define X(a, b, c, n, e)                                                                    \
-    if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.var == e)  \
-        return launch_round_t<a, b, c, n, e>(stream, imgs, cnt, tile_img, tile_last, ntiles, \
-                                             round, lut, grid_blocks, hist_bits, hist_round, wl, \
-                                             round_base, kflags);
+    // The bit-flag variants keep u8 images as u8 in LDS: a launch with
+    // kOnlyU8 takes that instantiation.
+    const bool u8 = (kflags & kOnlyU8) != 0;
+#define X(a, b, c, n, e)                                                                      \
+    if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.var == e) {  \
+        if constexpr (e == kVarBits || e == kVarBitsSeeded)                                   \
+            if (u8)                                                                           \
+                return launch_round_t<a, b, c, n, e, uint8_t>(stream, imgs, cnt, tile_img,    \
+                                                              tile_last, ntiles, round, lut,   \
+                                                              num_cus, hist_bits,              \
+                                                              hist_round, wl, round_base,      \
+                                                              kflags);                         \
+        return launch_round_t<a, b, c, n, e, uint16_t>(stream, imgs, cnt, tile_img, tile_last, \
+                                                       ntiles, round, lut, num_cus,             \
+                                                       hist_bits, hist_round, wl, round_base,   \
+                                                       kflags);                                 \
+    }
     THIN_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
@@ -1424,11 +1567,20 @@ hipError_t launch_coop(hipStream_t stream, TileShape shape, const ImgDev* imgs, 
                        int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round,
                        int kflags)
 {
-#define X(a, b, c, n, e)                                                                    \
-    if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.var == e)  \
-        return launch_coop_t<a, b, c, n, e>(stream, imgs, cnt, tile_img, tile_last, ntiles,  \
-                                            lut, active, rounds_out, max_rounds, num_cus,    \
-                                            hist_bits, hist_round, kflags);
+    const bool u8 = (kflags & kOnlyU8) != 0;
+#define X(a, b, c, n, e)                                                                      \
+    if (shape.th == a && shape.tw == b && shape.k == c && shape.nt == n && shape.var == e) {  \
+        if constexpr (e == kVarBits || e == kVarBitsSeeded)                                   \
+            if (u8)                                                                           \
+                return launch_coop_t<a, b, c, n, e, uint8_t>(stream, imgs, cnt, tile_img,     \
+                                                             tile_last, ntiles, lut, active,   \
+                                                             rounds_out, max_rounds, num_cus,  \
+                                                             hist_bits, hist_round, kflags);   \
+        return launch_coop_t<a, b, c, n, e, uint16_t>(stream, imgs, cnt, tile_img, tile_last,  \
+                                                      ntiles, lut, active, rounds_out,          \
+                                                      max_rounds, num_cus, hist_bits,           \
+                                                      hist_round, kflags);                      \
+    }
     THIN_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;

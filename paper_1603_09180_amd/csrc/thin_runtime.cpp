@@ -224,10 +224,37 @@ int ensure_snap(thin_ctx* ctx, size_t n)
     return THIN_OK;
 }
 
+bool bits_variant(TileShape s) { return s.var == thin::kVarBits || s.var == thin::kVarBitsSeeded; }
+
+// One round: a single launch, or for the bit-flag variants (whose LDS tile
+// has the image's pixel type) one launch per pixel type present.  dtypes:
+// bit 0 when u8 images take part, bit 1 when u16 ones do.
+hipError_t launch_rounds_split(hipStream_t stream, TileShape shape, const ImgDev* imgs,
+                               ImgCnt* cnt, const int32_t* tile_img, int32_t* tile_last,
+                               int ntiles, int round, const TopoEntry* lut, int num_cus,
+                               uint32_t* hist_bits, int32_t* hist_round, thin::WorkList wl,
+                               const int32_t* round_base, int kflags, int dtypes)
+{
+    if (!bits_variant(shape))
+        return thin::launch_round(stream, shape, imgs, cnt, tile_img, tile_last, ntiles, round, lut,
+                                  num_cus, hist_bits, hist_round, wl, round_base, kflags);
+    hipError_t e = hipSuccess;
+    if (dtypes & 1)
+        e = thin::launch_round(stream, shape, imgs, cnt, tile_img, tile_last, ntiles, round, lut,
+                               num_cus, hist_bits, hist_round, wl, round_base,
+                               kflags | thin::kOnlyU8);
+    if (e == hipSuccess && (dtypes & 2))
+        e = thin::launch_round(stream, shape, imgs, cnt, tile_img, tile_last, ntiles, round, lut,
+                               num_cus, hist_bits, hist_round, wl, round_base,
+                               kflags | thin::kOnlyU16);
+    return e;
+}
+
 // Launches one round, bracketed by timing events when profiling.
 int timed_round(thin_ctx* ctx, size_t& ev_used, TileShape shape, const ImgDev* imgs, ImgCnt* cnt,
                 const int32_t* tile_img, int32_t* tile_last, int ntiles, int round, int grid,
-                uint32_t* hist_bits, int32_t* hist_round, thin::WorkList wl, int kflags)
+                uint32_t* hist_bits, int32_t* hist_round, thin::WorkList wl, int kflags,
+                int dtypes)
 {
     if (ctx->profile) {
         while (ctx->prof_ev.size() < ev_used + 2) {
@@ -237,9 +264,10 @@ int timed_round(thin_ctx* ctx, size_t& ev_used, TileShape shape, const ImgDev* i
         }
         HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used], ctx->stream));
     }
-    HIP_TRY(ctx, thin::launch_round(ctx->stream, shape, imgs, cnt, tile_img, tile_last, ntiles,
-                                    round, ctx->d_lut, grid, hist_bits, hist_round, wl, nullptr,
-                                    kflags));
+    (void)grid;
+    HIP_TRY(ctx, launch_rounds_split(ctx->stream, shape, imgs, cnt, tile_img, tile_last, ntiles,
+                                     round, ctx->d_lut, ctx->num_cus, hist_bits, hist_round, wl,
+                                     nullptr, kflags, dtypes));
     if (ctx->profile) {
         HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used + 1], ctx->stream));
         ev_used += 2;
@@ -477,6 +505,8 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
         return true;
     };
     const int kflags = thin::kStateIsTile | (nimg == 1 ? thin::kOneImage : 0);
+    int dtypes = 0;
+    for (const ImgDev& d : plan.imgs) dtypes |= d.dtype == THIN_U8 ? 1 : 2;
     // Graph mode: a chunk of rounds is one graph replay; the launches read
     // their round from a device counter that the graph's last node advances.
     const bool use_graph = ctx->graph && !ctx->profile;
@@ -484,10 +514,11 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
     if (use_graph) HIP_TRY(ctx, hipMemsetAsync(d_round, 0, sizeof(int32_t), ctx->stream));
     auto record_rounds = [&](hipStream_t st, int count) -> hipError_t {
         for (int k = 0; k < count; ++k) {
-            const hipError_t e = thin::launch_round(st, shape, d_imgs, d_cnt, d_tile_img,
-                                                    d_tile_last, ntiles, k, ctx->d_lut, grid,
-                                                    d_hist_bits, d_hist_round, wl, d_round,
-                                                    kflags);
+            const hipError_t e = launch_rounds_split(st, shape, d_imgs, d_cnt, d_tile_img,
+                                                     d_tile_last, ntiles, k, ctx->d_lut,
+                                                     ctx->num_cus,
+                                                     d_hist_bits, d_hist_round, wl, d_round,
+                                                     kflags, dtypes);
             if (e != hipSuccess) return e;
         }
         return thin::launch_advance(st, d_round, count);
@@ -517,7 +548,7 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
             for (int k = 0; k < n; ++k) {
                 if ((rc = timed_round(ctx, ev_used, shape, d_imgs, d_cnt, d_tile_img, d_tile_last,
                                       ntiles, launched, grid, d_hist_bits, d_hist_round, wl,
-                                      kflags)))
+                                      kflags, dtypes)))
                     return rc;
                 ++launched;
             }
@@ -577,8 +608,17 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
 int run_coop(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work, thin_stats* stats)
 {
     int64_t total_px = 0;
-    for (int i : work) total_px += ims[i].h * ims[i].w;
-    const TileShape shape = choose_shape(ctx, total_px, (int64_t)work.size());
+    int dtypes = 0;
+    for (int i : work) {
+        total_px += ims[i].h * ims[i].w;
+        dtypes |= ims[i].dtype == THIN_U8 ? 1 : 2;
+    }
+    TileShape shape = choose_shape(ctx, total_px, (int64_t)work.size());
+    // One cooperative launch runs every image, so a bit-flag shape (LDS tile
+    // in the pixel type) needs a single pixel type; mixed calls take the flag
+    // variant.
+    if (bits_variant(shape) && dtypes == 3) shape = TileShape{64, 64, 16, 512, thin::kVarFlags};
+    const int coop_flags = bits_variant(shape) ? (dtypes == 1 ? thin::kOnlyU8 : thin::kOnlyU16) : 0;
     if (!thin::tile_shape_supported(shape))
         return fail(ctx, THIN_EINVAL, "unsupported tile shape %dx%d k=%d", shape.th, shape.tw, shape.k);
     const int K = shape.k;
@@ -660,7 +700,8 @@ int run_coop(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
                                    ntiles, ctx->d_lut, d_small, d_small + 3, rounds_cap,
                                    ctx->num_cus, static_cast<uint32_t*>(ctx->hist_bits.ptr),
                                    static_cast<int32_t*>(ctx->hist_round.ptr),
-                                   thin::kStateIsTile | (nimg == 1 ? thin::kOneImage : 0)));
+                                   thin::kStateIsTile | (nimg == 1 ? thin::kOneImage : 0) |
+                                       coop_flags));
     if (ctx->profile) {
         HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[1], ctx->stream));
         ev_used = 2;
@@ -1214,6 +1255,8 @@ int thin_serve_step(thin_ctx* ctx, int32_t rounds, uint64_t* done_tags, thin_sta
             ctx->serve_dirty = false;
         }
         const int ntiles = ctx->serve_ntiles;
+        int dtypes = 0;
+        for (const Resident& r : ctx->resident) dtypes |= r.img.dtype == THIN_U8 ? 1 : 2;
         const int grid = ctx->num_cus * thin::round_blocks_per_cu(shape);
         size_t ev_used = 0;
         for (int k = 0; k < rounds; ++k) {
@@ -1222,7 +1265,7 @@ int thin_serve_step(thin_ctx* ctx, int32_t rounds, uint64_t* done_tags, thin_sta
                                   ntiles, ctx->serve_round + k, grid,
                                   static_cast<uint32_t*>(ctx->hist_bits.ptr),
                                   static_cast<int32_t*>(ctx->hist_round.ptr), thin::WorkList{},
-                                  0)))
+                                  0, dtypes)))
                 return rc;
         }
         ctx->serve_round += rounds;

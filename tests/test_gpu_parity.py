@@ -269,3 +269,22 @@ def test_autotune_leaves_inputs_and_results_unchanged():
         sts = ctx.run_batch(ts, lams, adjs)
     for F, t, st, lam, adj in zip(Fs, ts, sts, lams, adjs):
         assert_same(F, lam, adj, t.cpu().numpy(), st)
+
+
+@pytest.mark.parametrize("variant", [3, 4])
+@pytest.mark.parametrize("engine", ENGINES[:2])
+def test_mixed_dtype_batch_bit_flag_variants(variant, engine):
+    """The bit-flag variants keep a u8 or u16 LDS tile per launch: a batch of
+    both pixel types runs as two launches per round (one cooperative launch
+    falls back to the flag variant)."""
+    Fs = [synth.gen_blobs(70 + 29 * i, 90 + 17 * i, 800 + i, np.uint16 if i % 3 == 0 else np.uint8,
+                          nblobs=8, sigma=(2.0, 10.0)) for i in range(9)]
+    lams = [0, 7, 300, 20, 0, 2000, 50, 3, 0]
+    adjs = [i % 2 for i in range(9)]
+    ts = [torch.from_numpy(F.copy()).cuda() for F in Fs]
+    say("case mixed dtypes variant", variant, "engine", engine)
+    with thin.Context(tile=64, steps_per_round=16, threads=256, variant=variant,
+                      engine=engine) as ctx:
+        sts = ctx.run_batch(ts, lams, adjs)
+    for F, t, st, lam, adj in zip(Fs, ts, sts, lams, adjs):
+        assert_same(F, lam, adj, t.cpu().numpy(), st)
