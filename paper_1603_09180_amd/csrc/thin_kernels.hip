@@ -893,20 +893,23 @@ __device__ __forceinline__ int wave_inclusive_sum(int v)
     return v;
 }
 
-// Residency with bit flags and dense work lists.  The re-examination flags
-// are one bit per lattice cell and parity class (4 bitmaps of LAT_H rows of
-// LWW words).  Each step, every wave takes the flagged candidates of its
-// class inside the exact region from its run of bitmap words (one word per
-// lane), clears those bits and writes
-// the candidates into its own list in LDS at offsets from a wave prefix sum;
-// after one barrier the block examines the concatenated lists densely, so
-// clean candidates cost nothing beyond their share of one word.  A lowered pixel sets the
-// bits of its whole 3x3 (section 2.2 re-examination rule, as in the other
-// variants).  With SEED, the initial flags of round r > 0 come from the
-// change bitmaps of round r - 1 (the pixels that tiles lowered during their
-// last 4 steps), dilated by the 3x3, instead of all ones: a candidate whose
-// 3x3 saw none of those changes was examined 4 steps earlier at the same
-// values.
+// Residency with bit flags and dense work lists.  Two sets of bitmaps, one
+// bit per lattice cell and parity class (4 x LAT_H rows of LWW words each):
+// "pending" holds the candidates to examine from the residency's start (all
+// ones, or with SEED from the previous round's change bitmaps), "lowered"
+// holds, per class, the cells lowered by that class's latest step.  A step
+// of class c needs the candidates whose 3x3 changed since their examination
+// 4 steps earlier (section 2.2 re-examination rule): the cell itself if it
+// was lowered then, and any pixel of its 3x3 lowered by the 3 steps since,
+// one class each; the owner of each bitmap word gathers those from the
+// lowered bitmaps with word shifts (pull), so a lowering costs one LDS
+// atomic.  Every wave takes the candidates of its run of words (one word per
+// lane), writes them into its own list in LDS at offsets from a wave prefix
+// sum, and after one barrier the block examines the concatenated lists
+// densely, so clean candidates cost nothing beyond their share of one word.
+// The seeded start: a candidate whose 3x3 saw none of the pixels lowered
+// during the last 4 steps of round r - 1 (dilated by the 3x3) was examined 4
+// steps earlier at the same values.
 template <int TH, int TW, int K, int NT, bool SEED, typename E>
 struct BTile {
     using Elem = E;  // LDS pixel type: the image's own
@@ -926,9 +929,9 @@ struct BTile {
     static constexpr int WAVE_WORDS = WAVE_ROWS * LWW;
     static constexpr int WAVE_CAP = WAVE_ROWS * LAT_W;              // cells of those rows
     static constexpr int LIST_ELEMS = NWAVE * WAVE_CAP;
-    // LDS bytes behind the flag pointer: 4 bitmaps, the wave lists and the
-    // wave list lengths
-    static constexpr int DIRTY_ELEMS = 16 * CLASS_WORDS + 2 * LIST_ELEMS + 4 * NWAVE;
+    // LDS bytes behind the flag pointer: 4 pending bitmaps, 4 lowered
+    // bitmaps, the wave lists and the wave list lengths
+    static constexpr int DIRTY_ELEMS = 32 * CLASS_WORDS + 2 * LIST_ELEMS + 4 * NWAVE;
     static constexpr int WPR = TW >= 32 ? TW / 32 : 1;
     static constexpr int RWW = (RW + 31) / 32;
     static constexpr int BITS_WORDS = SEED ? TH * WPR : 1;
@@ -983,7 +986,8 @@ struct BTile {
     {
         (void)t0;  // a multiple of 4: step tau has class tau mod 4
         uint32_t* s_db = reinterpret_cast<uint32_t*>(s_flags);           // [4][LAT_H][LWW]
-        uint16_t* s_list = reinterpret_cast<uint16_t*>(s_db + 4 * CLASS_WORDS);
+        uint32_t* s_dl = s_db + 4 * CLASS_WORDS;                         // [4][LAT_H][LWW]
+        uint16_t* s_list = reinterpret_cast<uint16_t*>(s_dl + 4 * CLASS_WORDS);
         int* s_wlen = reinterpret_cast<int*>(s_list + LIST_ELEMS);
         const int ry0 = gy0 - K, rx0 = gx0 - K;
         const bool seeded = SEED && sd != nullptr && sd->r > 0;
@@ -993,6 +997,7 @@ struct BTile {
         }
         if constexpr (SEED)
             for (int i = tid; i < TH * WPR; i += NT) s_bits[i] = 0u;
+        for (int i = tid; i < 4 * CLASS_WORDS; i += NT) s_dl[i] = 0u;
         if (!seeded) {
             for (int i = tid; i < 4 * CLASS_WORDS; i += NT) s_db[i] = valid_bits(i % LWW);
         } else if constexpr (SEED) {
@@ -1058,14 +1063,42 @@ struct BTile {
             const int a_lo = (r_lo - si + 1) >> 1, a_hi = (r_hi - si) >> 1;
             const int b_lo = (c_lo - sj + 1) >> 1, b_hi = (c_hi - sj) >> 1;
             uint32_t take = 0u;
-            if (myw < CLASS_WORDS && wa >= a_lo && wa <= a_hi) {
+            if (myw < CLASS_WORDS) {
+                // Candidates of this word to examine: still pending from the
+                // residency's start, lowered themselves 4 steps ago, or next to
+                // a pixel lowered during the last 3 steps (the lowered bitmap
+                // of each other class, spread over the cells whose 3x3 holds
+                // it: rows a or a+-1 and columns b or b+-1 by parity).
+                uint32_t want = s_db[c * CLASS_WORDS + myw] | s_dl[c * CLASS_WORDS + myw];
+                s_db[c * CLASS_WORDS + myw] = 0u;
+                s_dl[c * CLASS_WORDS + myw] = 0u;
+#pragma unroll
+                for (int k = 1; k < 4; ++k) {
+                    const int o = (c + k) & 3, oi = o >> 1, oj = o & 1;
+                    const uint32_t* lo_bm = s_dl + o * CLASS_WORDS;
+                    const int r0 = oi == si ? wa : (oi > si ? wa - 1 : wa);
+                    const int nr = oi == si ? 1 : 2;
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int row = r0 + q;
+                        if (q >= nr || row < 0 || row >= LAT_H) continue;
+                        const uint32_t* rw = lo_bm + row * LWW;
+                        const uint32_t w = rw[wj];
+                        if (oj == sj) {
+                            want |= w;
+                        } else if (oj > sj) {  // cells b - 1 and b
+                            const uint32_t prev = wj > 0 ? rw[wj - 1] : 0u;
+                            want |= w | (w << 1) | (prev >> 31);
+                        } else {               // cells b and b + 1
+                            const uint32_t next = wj + 1 < LWW ? rw[wj + 1] : 0u;
+                            want |= w | (w >> 1) | (next << 31);
+                        }
+                    }
+                }
                 const int lo = max(b_lo - 32 * wj, 0), hi = min(b_hi - 32 * wj, 31);
-                if (lo <= hi) {
+                if (wa >= a_lo && wa <= a_hi && lo <= hi) {
                     const uint32_t mask = (hi == 31 ? ~0u : ((2u << hi) - 1u)) & ~((1u << lo) - 1u);
-                    uint32_t* p = s_db + c * CLASS_WORDS + myw;
-                    const uint32_t w = *p;
-                    take = w & mask;
-                    if (take) *p = w & ~mask;
+                    take = want & mask;
                 }
             }
             const int cnt = __popc(take);
@@ -1102,17 +1135,7 @@ struct BTile {
                 uint32_t alpha;
                 if (decide(v, nbv, lut, lambda, alpha)) {
                     p[0] = (E)alpha;
-#pragma unroll
-                    for (int dy = -1; dy <= 1; ++dy) {
-                        const int y = lr + dy;
-#pragma unroll
-                        for (int dx = -1; dx <= 1; ++dx) {
-                            const int x = lc + dx;
-                            const int cc = ((y & 1) << 1) | (x & 1), bb = x >> 1;
-                            atomicOr(&s_db[cc * CLASS_WORDS + (y >> 1) * LWW + (bb >> 5)],
-                                     1u << (bb & 31));
-                        }
-                    }
+                    atomicOr(&s_dl[c * CLASS_WORDS + a * LWW + (b >> 5)], 1u << (b & 31));
                     if (lr >= K && lr < K + TH && lc >= K && lc < K + TW) {
                         ++my_count;
                         inner = true;

@@ -330,13 +330,11 @@ TileShape choose_shape(const thin_ctx* ctx, int64_t total_pixels, int64_t images
     if (it != ctx->tuned.end()) return it->second;
     // Small work lists are bound by the latency of each round: small tiles
     // with one cell per thread and register windows.  Large ones are bound by
-    // throughput: dense per-step work lists with seeded flags, in big tiles
-    // (less halo work) when the images are large, else in 64x64 tiles with
-    // 256-thread blocks, several per CU.
+    // throughput: dense per-step work lists with seeded flags in 128x128
+    // tiles (less halo work per pixel).
+    (void)images;
     if (total_pixels <= (int64_t)1 << 20) return TileShape{32, 32, 16, 1024, thin::kVarRegs};
-    if (total_pixels >= ((int64_t)4 << 20) * std::max<int64_t>(images, 1))
-        return TileShape{128, 128, 16, 512, thin::kVarBitsSeeded};
-    return TileShape{64, 64, 16, 256, thin::kVarBitsSeeded};
+    return TileShape{128, 128, 16, 512, thin::kVarBitsSeeded};
 }
 
 void fill_stats(thin_stats* st, const ImgCnt& c, int steps_done, int max_steps, bool trivial)
