@@ -904,9 +904,10 @@ __device__ __forceinline__ int wave_inclusive_sum(int v)
 // one class each; the owner of each bitmap word gathers those from the
 // lowered bitmaps with word shifts (pull), so a lowering costs one LDS
 // atomic.  Every wave takes the candidates of its run of words (one word per
-// lane), writes them into its own list in LDS at offsets from a wave prefix
-// sum, and after one barrier the block examines the concatenated lists
-// densely, so clean candidates cost nothing beyond their share of one word.
+// lane) and writes them into a run of the step's list that it reserves with
+// one LDS atomic, at offsets from a wave prefix sum; after one barrier the
+// block examines the list densely, so clean candidates cost nothing beyond
+// their share of one word.
 // The seeded start: a candidate whose 3x3 saw none of the pixels lowered
 // during the last 4 steps of round r - 1 (dilated by the 3x3) was examined 4
 // steps earlier at the same values.
@@ -923,15 +924,14 @@ struct BTile {
     static constexpr int CLASS_WORDS = LAT_H * LWW;   // bitmap words per class
     static constexpr int NWAVE = NT / 64;
     // Bitmap words of a class are dealt to the waves in runs of WAVE_WORDS
-    // (one per lane), so the wave lists, concatenated, are in raster order
-    // and neighbouring lanes examine neighbouring cells.
-    static constexpr int WAVE_ROWS = (LAT_H + NWAVE - 1) / NWAVE;  // whole lattice rows
+    // (one per lane, whole lattice rows), so each wave's run of the list is
+    // in raster order and neighbouring lanes examine neighbouring cells.
+    static constexpr int WAVE_ROWS = (LAT_H + NWAVE - 1) / NWAVE;
     static constexpr int WAVE_WORDS = WAVE_ROWS * LWW;
-    static constexpr int WAVE_CAP = WAVE_ROWS * LAT_W;              // cells of those rows
-    static constexpr int LIST_ELEMS = NWAVE * WAVE_CAP;
+    static constexpr int LIST_ELEMS = (NCELL + 1) & ~1;
     // LDS bytes behind the flag pointer: 4 pending bitmaps, 4 lowered
-    // bitmaps, the wave lists and the wave list lengths
-    static constexpr int DIRTY_ELEMS = 32 * CLASS_WORDS + 2 * LIST_ELEMS + 4 * NWAVE;
+    // bitmaps, the step's list and two list lengths
+    static constexpr int DIRTY_ELEMS = 32 * CLASS_WORDS + 2 * LIST_ELEMS + 8;
     static constexpr int WPR = TW >= 32 ? TW / 32 : 1;
     static constexpr int RWW = (RW + 31) / 32;
     static constexpr int BITS_WORDS = SEED ? TH * WPR : 1;
@@ -941,8 +941,7 @@ struct BTile {
     static_assert(TH % 4 == 0 && TW % 4 == 0, "tile sides must be multiples of 4");
     static_assert(NT % 64 == 0 && CLASS_WORDS <= NT, "one bitmap word per thread");
     static_assert(WAVE_WORDS <= 64, "one bitmap word per lane");
-    static_assert(LIST_ELEMS >= NCELL, "wave lists hold every cell");
-    static_assert(NCELL < 65536, "list entries are 16-bit");
+    static_assert(LAT_H <= 256 && LAT_W <= 256, "list entries hold a row and a column byte");
     static_assert(!SEED || TW % 32 == 0, "history bitmaps need a tile width multiple of 32");
     static_assert(!SEED || 2 * K <= TH, "history seeding needs the region inside the 3x3 tile block");
 
@@ -988,7 +987,7 @@ struct BTile {
         uint32_t* s_db = reinterpret_cast<uint32_t*>(s_flags);           // [4][LAT_H][LWW]
         uint32_t* s_dl = s_db + 4 * CLASS_WORDS;                         // [4][LAT_H][LWW]
         uint16_t* s_list = reinterpret_cast<uint16_t*>(s_dl + 4 * CLASS_WORDS);
-        int* s_wlen = reinterpret_cast<int*>(s_list + LIST_ELEMS);
+        int* s_total = reinterpret_cast<int*>(s_list + LIST_ELEMS);  // [2], by step parity
         const int ry0 = gy0 - K, rx0 = gx0 - K;
         const bool seeded = SEED && sd != nullptr && sd->r > 0;
         if (tid == 0) {
@@ -998,6 +997,7 @@ struct BTile {
         if constexpr (SEED)
             for (int i = tid; i < TH * WPR; i += NT) s_bits[i] = 0u;
         for (int i = tid; i < 4 * CLASS_WORDS; i += NT) s_dl[i] = 0u;
+        if (tid == 0) s_total[0] = s_total[1] = 0;
         if (!seeded) {
             for (int i = tid; i < 4 * CLASS_WORDS; i += NT) s_db[i] = valid_bits(i % LWW);
         } else if constexpr (SEED) {
@@ -1052,7 +1052,6 @@ struct BTile {
         const int wave = tid >> 6, lane = tid & 63;
         const int myw = lane < WAVE_WORDS ? wave * WAVE_WORDS + lane : CLASS_WORDS;  // its word
         const int wa = myw / LWW, wj = myw - (myw / LWW) * LWW;
-        uint16_t* my_list = s_list + wave * WAVE_CAP;
         int my_count = 0;
         for (int tau = 0; tau < nsteps; ++tau) {
             const int c = tau & 3, si = c >> 1, sj = c & 1;
@@ -1101,32 +1100,31 @@ struct BTile {
                     take = want & mask;
                 }
             }
+            // Each wave reserves a run of the step's list with one LDS atomic
+            // (the counter of the other parity was read a step ago and is
+            // cleared for the next step while this one is examined).
             const int cnt = __popc(take);
             const int incl = wave_inclusive_sum(cnt);
-            if (lane == 63) s_wlen[wave] = incl;
+            const int wave_total = __builtin_amdgcn_readlane(incl, 63);
+            int base = 0;
+            if (lane == 63 && wave_total) base = atomicAdd(&s_total[tau & 1], wave_total);
+            base = __builtin_amdgcn_readlane(base, 63);
             if (take) {
-                int off = incl - cnt;
-                const int cell0 = wa * LAT_W + 32 * wj;
+                int off = base + incl - cnt;
                 uint32_t t = take;
                 while (t) {
-                    my_list[off++] = (uint16_t)(cell0 + __ffs(t) - 1);
+                    // entry: lattice row in the high byte, column in the low
+                    s_list[off++] = (uint16_t)((wa << 8) | (32 * wj + __ffs(t) - 1));
                     t &= t - 1u;
                 }
             }
             __syncthreads();
-            // The wave lists, concatenated, are examined by the whole block.
-            int start[NWAVE + 1];
-            start[0] = 0;
-#pragma unroll
-            for (int wv = 0; wv < NWAVE; ++wv) start[wv + 1] = start[wv] + s_wlen[wv];
-            const int total = start[NWAVE];
+            const int total = s_total[tau & 1];
+            if (tid == 0) s_total[(tau + 1) & 1] = 0;
             bool inner = false;
             for (int i = tid; i < total; i += NT) {
-                int wv = 0;
-#pragma unroll
-                for (int q = 1; q < NWAVE; ++q) wv += i >= start[q] ? 1 : 0;
-                const int cell = s_list[wv * WAVE_CAP + i - start[wv]];
-                const int a = cell / LAT_W, b = cell - a * LAT_W;
+                const int cell = s_list[i];
+                const int a = cell >> 8, b = cell & 0xFF;
                 const int lr = 2 * a + si, lc = 2 * b + sj;
                 E* p = s_img + lr * RWP + lc;
                 const uint32_t v = p[0];
