@@ -321,6 +321,7 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512, tune=True
             "traffic": _traffic_for("k_round", "batch_512"),
             "launches_per_step": launches,
             "avg_launch_us": round(kernel_ms * 1e3 / max(launches, 1), 3),
+            "alg_bytes_per_launch": round(alg_one / max(launches, 1), 1),
             "timing": "kernel durations from HIP events in a second pass over the same batch",
         },
     }
