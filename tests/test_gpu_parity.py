@@ -288,3 +288,31 @@ def test_mixed_dtype_batch_bit_flag_variants(variant, engine):
         sts = ctx.run_batch(ts, lams, adjs)
     for F, t, st, lam, adj in zip(Fs, ts, sts, lams, adjs):
         assert_same(F, lam, adj, t.cpu().numpy(), st)
+
+
+@pytest.mark.parametrize("shape", ["32,32,16,256,0", "32,32,16,1024,2", "64,64,16,256,4"])
+def test_work_lists_match_full_scans(shape, monkeypatch):
+    """A batch with many more tiles than blocks runs on per-round tile queues
+    (round 0 visits every tile, later rounds the tiles queued by the round
+    before); each image must equal its own run, where every tile is scanned
+    every round, and a sample the oracle."""
+    monkeypatch.setenv("THIN_TILE_SHAPE", shape)
+    rng = np.random.default_rng(61)
+    Fs = []
+    for i in range(120):
+        h, w = (int(x) for x in rng.integers(150, 520, size=2))
+        Fs.append(synth.gen_blobs(h, w, 6100 + i, np.uint16 if i % 5 == 0 else np.uint8,
+                                  nblobs=10, sigma=(3.0, 14.0)))
+    lams = [int(x) for x in rng.choice([0, 5, 20, 50], size=len(Fs))]
+    adjs = [i % 2 for i in range(len(Fs))]
+    say("case work lists", shape)
+    batch = [torch.from_numpy(F.copy()).cuda() for F in Fs]
+    with thin.Context() as ctx:
+        sts = ctx.run_batch(batch, lams, adjs)
+        for i, F in enumerate(Fs):
+            t = torch.from_numpy(F.copy()).cuda()
+            st = ctx.run(t, lams[i], adjs[i])
+            assert torch.equal(t, batch[i]), i
+            assert (st.passes, st.lowerings) == (sts[i].passes, sts[i].lowerings), i
+    for i in range(0, len(Fs), 15):
+        assert_same(Fs[i], lams[i], adjs[i], batch[i].cpu().numpy(), sts[i])
