@@ -68,10 +68,8 @@ enum {
     THIN_ENGINE_TILED = 1,    /* one launch per round of LDS tiles (several parity steps per
                                  residency, stable tiles skipped); the host checks convergence */
     THIN_ENGINE_STEP = 2,     /* one parity step per launch over global memory (simple, slow) */
-    THIN_ENGINE_PERSIST = 3,  /* one launch for the whole run: the same tiles taken from an
-                                 in-order work queue, each waiting only for its neighbouring
-                                 tiles' previous round.  Currently disabled: calls return
-                                 THIN_EINVAL */
+    THIN_ENGINE_PERSIST = 3,  /* reserved (a persistent work-queue engine; not available:
+                                 calls return THIN_EINVAL) */
     THIN_ENGINE_COOP = 4      /* one cooperative launch for the whole run: the tiled engine's
                                  rounds separated by grid-wide barriers; convergence decided
                                  on the device */

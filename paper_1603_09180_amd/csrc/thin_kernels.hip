@@ -15,16 +15,19 @@
 //   contain a pixel y with v - F(y) <= lambda;
 //   a lambda-destructible x gets F(x) := alpha- = max F over L.
 //
-// Two engines:
+// Kernels:
 //   k_step   one parity step per launch, straight from global memory;
-//   k_round  LDS tiles with a halo of K pixels: one residency runs K parity
-//            steps (the exact region shrinks by one pixel per step), reading
-//            one ping-pong buffer and writing the other.  A tile whose 3x3
-//            tile neighbourhood lowered nothing during the last 4 steps
-//            cannot lower anything in the coming K steps (K <= tile side:
-//            every pixel it could read was already examined at the same
-//            values), so it is skipped; it only copies itself across the
-//            ping-pong pair when it changed during the previous round.
+//   k_round  one round: LDS tiles with a halo of K pixels, one residency
+//            running K parity steps (the exact region shrinks by one pixel
+//            per step), reading one ping-pong buffer and writing the other.
+//            A tile whose 3x3 tile neighbourhood lowered nothing during the
+//            last 4 steps cannot lower anything in the coming K steps
+//            (K <= tile side: every pixel it could read was already examined
+//            at the same values), so it is skipped; it only copies itself
+//            across the ping-pong pair when it changed during the previous
+//            round.  Residency variants (Tile, RTile, BTile) differ only in
+//            how a step finds and examines its candidates;
+//   k_coop   the rounds of k_round in one cooperative launch.
 #include "thin_internal.h"
 
 #include <climits>
