@@ -89,3 +89,16 @@ def test_table_matches_oracle_characterisation(lib, adj):
         assert all(m == 0 for m in masks[pt.tminus:]), mask
         assert all(m & mask == 0 for m in masks), mask          # components lie in L
         assert got == sorted(pt.comp_max), mask
+
+
+def test_table_destructible_bit_is_the_yokoi_number():
+    """The table's destructible bit against a closed form: the
+    Yokoi-Toriwaki-Fukumura connectivity number of the upper mask (over the
+    ring's 4-neighbour positions, on L for (8,4), on U for (4,8)) equals 1
+    exactly for the destructible masks."""
+    for adj in (thin.THIN_ADJ_8_4, thin.THIN_ADJ_4_8):
+        table = thin.thin_topology_table(adj)
+        for m, (flags, _) in enumerate(table):
+            b = [((m >> p) & 1) ^ (1 if adj == thin.THIN_ADJ_8_4 else 0) for p in range(8)]
+            n = sum(b[k] - b[k] * b[(k + 1) % 8] * b[(k + 2) % 8] for k in (0, 2, 4, 6))
+            assert (flags & 1) == (1 if n == 1 else 0), (adj, m)
