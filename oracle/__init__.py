@@ -1,4 +1,5 @@
-"""CPU oracle for the lambda-leveling loop (test infrastructure only).
+"""CPU oracle for the lambda-leveling loop and the lambda-skeleton (test
+infrastructure only).
 
 Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  The product library never calls it, and the two share no
@@ -8,11 +9,14 @@ code: the oracle computes every connectivity number by flood fill over the
 from .oracle import (  # noqa: F401
     ADJ_8_4,
     ADJ_4_8,
+    OP_LEVELING,
+    OP_SKELETON,
     OracleError,
     build,
     classify,
     classify_patch,
     count_destructible,
+    count_lowerable,
     queue,
     ring_offsets,
     sweep,

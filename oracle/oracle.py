@@ -16,6 +16,11 @@ import numpy as np
 ADJ_8_4 = 0
 ADJ_4_8 = 1
 
+# Operators (section 2.2): the lambda-leveling type set (lambda-destructible
+# points) and the lambda-skeleton's (lambda-deletable and not lambda-end).
+OP_LEVELING = 0
+OP_SKELETON = 1
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "thin_oracle.c")
 _LIB = os.path.join(_HERE, "libthin_oracle.so")
@@ -48,6 +53,11 @@ class _Point(ctypes.Structure):
         ("alpha_minus", ctypes.c_int64),
         ("comp_max", ctypes.c_int64 * 4),
         ("qualifying", ctypes.c_int32),
+        ("peak", ctypes.c_int32),
+        ("end", ctypes.c_int32),
+        ("lambda_deletable", ctypes.c_int32),
+        ("lambda_end", ctypes.c_int32),
+        ("skeleton", ctypes.c_int32),
         ("pad", ctypes.c_int32),
     ]
 
@@ -67,18 +77,18 @@ def _load():
         lib.oracle_classify.argtypes = [i64p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
                                         ctypes.POINTER(_Point)]
         lib.oracle_classify.restype = None
-        lib.oracle_sweep.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
-                                     ctypes.c_int32, ctypes.c_uint64, u64p, u64p]
+        img = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32,
+               ctypes.c_int32]  # F, h, w, lambda, adjacency, op
+        lib.oracle_sweep.argtypes = img + [ctypes.c_uint64, u64p, u64p]
         lib.oracle_sweep.restype = ctypes.c_int
-        lib.oracle_sweep_ordered.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
-                                             ctypes.c_int32, i64p, u64p, u64p]
+        lib.oracle_sweep_ordered.argtypes = img + [i64p, u64p, u64p]
         lib.oracle_sweep_ordered.restype = ctypes.c_int
-        lib.oracle_sweep_dirty.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
-                                           ctypes.c_int32, u64p, u64p, u64p]
+        lib.oracle_sweep_dirty.argtypes = img + [u64p, u64p, u64p]
         lib.oracle_sweep_dirty.restype = ctypes.c_int
-        lib.oracle_queue.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint32,
-                                     ctypes.c_int32, u64p, u64p]
+        lib.oracle_queue.argtypes = img + [u64p, u64p]
         lib.oracle_queue.restype = ctypes.c_int
+        lib.oracle_count_lowerable.argtypes = img + [u64p]
+        lib.oracle_count_lowerable.restype = ctypes.c_int
         lib.oracle_count_destructible.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64,
                                                   ctypes.c_uint32, ctypes.c_int32, u64p, u64p]
         lib.oracle_count_destructible.restype = ctypes.c_int
@@ -94,6 +104,14 @@ def _adj_code(adj) -> int:
     if adj in (ADJ_4_8, "4,8", (4, 8)):
         return ADJ_4_8
     raise ValueError(f"unknown adjacency {adj!r}")
+
+
+def _op_code(op) -> int:
+    if op in (OP_LEVELING, "leveling"):
+        return OP_LEVELING
+    if op in (OP_SKELETON, "skeleton"):
+        return OP_SKELETON
+    raise ValueError(f"unknown operator {op!r}")
 
 
 def _widen(F: np.ndarray) -> np.ndarray:
@@ -125,6 +143,11 @@ class Point:
     alpha_minus: int
     comp_max: list
     qualifying: int
+    peak: bool
+    end: bool
+    lambda_deletable: bool
+    lambda_end: bool
+    skeleton: bool
 
 
 def ring_offsets():
@@ -146,7 +169,8 @@ def classify(neighbours, centre: int, adj=ADJ_8_4, lam: int = 0) -> Point:
     k = out.tminus
     return Point(out.tplus, out.tminus, bool(out.destructible), bool(out.lambda_destr),
                  int(out.alpha_minus), [int(out.comp_max[i]) for i in range(min(k, 4))],
-                 out.qualifying)
+                 out.qualifying, bool(out.peak), bool(out.end), bool(out.lambda_deletable),
+                 bool(out.lambda_end), bool(out.skeleton))
 
 
 def classify_patch(patch, adj=ADJ_8_4, lam: int = 0) -> Point:
@@ -163,7 +187,7 @@ def _check(rc: int, what: str):
         raise OracleError(f"{what}: out of memory")
 
 
-def sweep(F, lam: int, adj=ADJ_8_4, max_passes: int = 0) -> SweepResult:
+def sweep(F, lam: int, adj=ADJ_8_4, max_passes: int = 0, op=OP_LEVELING) -> SweepResult:
     """ORACLE-SWEEP: four parity classes per pass, raster order, to stability."""
     lib = _load()
     src = np.asarray(F)
@@ -171,14 +195,14 @@ def sweep(F, lam: int, adj=ADJ_8_4, max_passes: int = 0) -> SweepResult:
     p = ctypes.c_uint64()
     lo = ctypes.c_uint64()
     rc = lib.oracle_sweep(_ptr(a, ctypes.c_int32), a.shape[0], a.shape[1],
-                          ctypes.c_uint32(int(lam)), _adj_code(adj), max_passes,
+                          ctypes.c_uint32(int(lam)), _adj_code(adj), _op_code(op), max_passes,
                           ctypes.byref(p), ctypes.byref(lo))
     _check(rc, "oracle_sweep")
     return SweepResult(a.astype(src.dtype, copy=False), p.value, lo.value,
                        limited=(rc == _ELIMIT))
 
 
-def sweep_ordered(F, lam: int, adj, order) -> SweepResult:
+def sweep_ordered(F, lam: int, adj, order, op=OP_LEVELING) -> SweepResult:
     """Sweep with an arbitrary visiting order inside each parity class."""
     lib = _load()
     src = np.asarray(F)
@@ -189,13 +213,13 @@ def sweep_ordered(F, lam: int, adj, order) -> SweepResult:
     p = ctypes.c_uint64()
     lo = ctypes.c_uint64()
     rc = lib.oracle_sweep_ordered(_ptr(a, ctypes.c_int32), a.shape[0], a.shape[1],
-                                  ctypes.c_uint32(int(lam)), _adj_code(adj),
+                                  ctypes.c_uint32(int(lam)), _adj_code(adj), _op_code(op),
                                   _ptr(order, ctypes.c_int64), ctypes.byref(p), ctypes.byref(lo))
     _check(rc, "oracle_sweep_ordered")
     return SweepResult(a.astype(src.dtype, copy=False), p.value, lo.value)
 
 
-def sweep_dirty(F, lam: int, adj=ADJ_8_4) -> SweepResult:
+def sweep_dirty(F, lam: int, adj=ADJ_8_4, op=OP_LEVELING) -> SweepResult:
     """ORACLE-SWEEP-DIRTY: same output, re-examining only pixels whose 3x3 changed."""
     lib = _load()
     src = np.asarray(F)
@@ -204,13 +228,13 @@ def sweep_dirty(F, lam: int, adj=ADJ_8_4) -> SweepResult:
     lo = ctypes.c_uint64()
     ex = ctypes.c_uint64()
     rc = lib.oracle_sweep_dirty(_ptr(a, ctypes.c_int32), a.shape[0], a.shape[1],
-                                ctypes.c_uint32(int(lam)), _adj_code(adj),
+                                ctypes.c_uint32(int(lam)), _adj_code(adj), _op_code(op),
                                 ctypes.byref(p), ctypes.byref(lo), ctypes.byref(ex))
     _check(rc, "oracle_sweep_dirty")
     return SweepResult(a.astype(src.dtype, copy=False), p.value, lo.value, ex.value)
 
 
-def queue(F, lam: int, adj=ADJ_8_4) -> SweepResult:
+def queue(F, lam: int, adj=ADJ_8_4, op=OP_LEVELING) -> SweepResult:
     """ORACLE-QUEUE: the paper's minimal-value order (section 2.2).  passes=0."""
     lib = _load()
     src = np.asarray(F)
@@ -218,7 +242,7 @@ def queue(F, lam: int, adj=ADJ_8_4) -> SweepResult:
     lo = ctypes.c_uint64()
     pops = ctypes.c_uint64()
     rc = lib.oracle_queue(_ptr(a, ctypes.c_int32), a.shape[0], a.shape[1],
-                          ctypes.c_uint32(int(lam)), _adj_code(adj),
+                          ctypes.c_uint32(int(lam)), _adj_code(adj), _op_code(op),
                           ctypes.byref(lo), ctypes.byref(pops))
     _check(rc, "oracle_queue")
     return SweepResult(a.astype(src.dtype, copy=False), 0, lo.value, pops.value)
@@ -235,3 +259,15 @@ def count_destructible(F, lam: int, adj=ADJ_8_4):
                                        ctypes.byref(ld), ctypes.byref(d))
     _check(rc, "oracle_count_destructible")
     return ld.value, d.value
+
+
+def count_lowerable(F, lam: int, adj=ADJ_8_4, op=OP_LEVELING) -> int:
+    """Interior pixels that operator op would lower (0 for a stable image)."""
+    lib = _load()
+    a = _widen(F)
+    c = ctypes.c_uint64()
+    rc = lib.oracle_count_lowerable(_ptr(a, ctypes.c_int32), a.shape[0], a.shape[1],
+                                    ctypes.c_uint32(int(lam)), _adj_code(adj), _op_code(op),
+                                    ctypes.byref(c))
+    _check(rc, "oracle_count_lowerable")
+    return c.value

@@ -25,7 +25,18 @@
  *   - x is k-divergent when T-- = k > 1;
  *   - x is lambda-destructible when it is destructible, or k-divergent with at
  *     least k-1 of the counted lower components c satisfying
- *     F(x) - m(c) <= lambda.
+ *     F(x) - m(c) <= lambda;
+ *   - x is a peak point when T+ = 0, and lambda-deletable when it is
+ *     lambda-destructible, or a peak with F(x) - alpha- <= lambda;
+ *   - x is an end point (for F) when exactly one of its n-neighbours lies in
+ *     the section F_k, k = F(x), and a lambda-end point when it is an end
+ *     point with F(x) - alpha- > lambda.
+ *
+ * Two operators, both "lower a point of the type set to alpha- until
+ * stability" (section 2.2), differ only in the type set:
+ *   op 0, lambda-leveling: the lambda-destructible points;
+ *   op 1, lambda-skeleton (the algorithm box of section 2.2): the points that
+ *         are lambda-deletable and not lambda-end.
  *
  * Readings of points the paper leaves open (listed with reasons in the design
  * notes of the repository):
@@ -122,6 +133,12 @@ typedef struct {
     int64_t comp_max[4];    /* m(c) of each counted lower component, in    */
                             /* order of first ring position; unused = -1    */
     int32_t qualifying;     /* #counted components with F(x) - m(c) <= lam  */
+    int32_t peak;           /* T+ = 0                                       */
+    int32_t end;            /* exactly one n-neighbour y with F(y) >= F(x)  */
+    int32_t lambda_deletable; /* lambda-destructible, or a peak with        */
+                            /* F(x) - alpha- <= lambda                      */
+    int32_t lambda_end;     /* end point with F(x) - alpha- > lambda        */
+    int32_t skeleton;       /* lambda-deletable and not lambda-end          */
     int32_t pad;
 } oracle_point;
 
@@ -166,7 +183,26 @@ void oracle_classify(const int64_t nb[8], int64_t v, int32_t adjacency, uint32_t
     }
     const int k = out->tminus;
     out->lambda_destr = out->destructible || (k > 1 && out->qualifying >= k - 1);
+
+    /* Peak and end points, and the skeleton's type set.  The contrast
+     * F(x) - alpha- is 0 when Gamma-- is empty (alpha- = F(x) then). */
+    const int64_t contrast = v - out->alpha_minus;
+    int upper_n_neighbours = 0;
+    for (int p = 0; p < 8; ++p)
+        if (upper[p] && offsets_adjacent(RING_DI[p], RING_DJ[p], n)) ++upper_n_neighbours;
+    out->peak = out->tplus == 0;
+    out->end = upper_n_neighbours == 1;
+    out->lambda_deletable = out->lambda_destr || (out->peak && contrast <= (int64_t)lambda);
+    out->lambda_end = out->end && contrast > (int64_t)lambda;
+    out->skeleton = out->lambda_deletable && !out->lambda_end;
     out->pad = 0;
+}
+
+/* Whether operator `op` lowers a characterised point (section 2.2: op 0 the
+ * lambda-destructible type set, op 1 the lambda-skeleton's). */
+static int lowerable(const oracle_point* pt, int32_t op)
+{
+    return op == 1 ? pt->skeleton : pt->lambda_destr;
 }
 
 /* Characterise interior pixel (i, j) of F (row-major, h x w). */
@@ -185,17 +221,19 @@ static const int CLASS_J[4] = {0, 1, 0, 1};
 enum { ORACLE_OK = 0, ORACLE_EINVAL = -1, ORACLE_ENOMEM = -2, ORACLE_ELIMIT = -4 };
 
 /*
- * ORACLE-SWEEP: lower lambda-destructible points until stability, visiting
- * the four parity classes in order, each in raster order, every interior
- * pixel of the class once per visit.
+ * ORACLE-SWEEP: lower the points of operator op's type set (op 0 the
+ * lambda-destructible points, op 1 the lambda-skeleton's) until stability,
+ * visiting the four parity classes in order, each in raster order, every
+ * interior pixel of the class once per visit.
  * max_passes = 0 means no cap; when the cap is reached before stability the
  * function returns ORACLE_ELIMIT with F holding the state after the last pass.
  * passes_out: passes run, including the final pass without any lowering.
  */
 int oracle_sweep(int32_t* F, int64_t h, int64_t w, uint32_t lambda, int32_t adjacency,
-                 uint64_t max_passes, uint64_t* passes_out, uint64_t* lowerings_out)
+                 int32_t op, uint64_t max_passes, uint64_t* passes_out, uint64_t* lowerings_out)
 {
-    if (h < 0 || w < 0 || (adjacency != 0 && adjacency != 1)) return ORACLE_EINVAL;
+    if (h < 0 || w < 0 || (adjacency != 0 && adjacency != 1) || (op != 0 && op != 1))
+        return ORACLE_EINVAL;
     uint64_t passes = 0, lowerings = 0;
     int status = ORACLE_OK;
     if (h >= 3 && w >= 3) {
@@ -209,7 +247,7 @@ int oracle_sweep(int32_t* F, int64_t h, int64_t w, uint32_t lambda, int32_t adja
                         if ((j & 1) != CLASS_J[s]) continue;
                         oracle_point pt;
                         classify_at(F, w, i, j, adjacency, lambda, &pt);
-                        if (pt.lambda_destr) {
+                        if (lowerable(&pt, op)) {
                             F[i * w + j] = (int32_t)pt.alpha_minus;
                             ++lowered_this_pass;
                         }
@@ -233,9 +271,11 @@ int oracle_sweep(int32_t* F, int64_t h, int64_t w, uint32_t lambda, int32_t adja
  * in any order must give the raster-order result bit for bit.
  */
 int oracle_sweep_ordered(int32_t* F, int64_t h, int64_t w, uint32_t lambda, int32_t adjacency,
-                         const int64_t* order, uint64_t* passes_out, uint64_t* lowerings_out)
+                         int32_t op, const int64_t* order, uint64_t* passes_out,
+                         uint64_t* lowerings_out)
 {
-    if (h < 0 || w < 0 || (adjacency != 0 && adjacency != 1) || !order) return ORACLE_EINVAL;
+    if (h < 0 || w < 0 || (adjacency != 0 && adjacency != 1) || (op != 0 && op != 1) || !order)
+        return ORACLE_EINVAL;
     uint64_t passes = 0, lowerings = 0;
     if (h >= 3 && w >= 3) {
         for (;;) {
@@ -247,7 +287,7 @@ int oracle_sweep_ordered(int32_t* F, int64_t h, int64_t w, uint32_t lambda, int3
                     if ((i & 1) != CLASS_I[s] || (j & 1) != CLASS_J[s]) continue;
                     oracle_point pt;
                     classify_at(F, w, i, j, adjacency, lambda, &pt);
-                    if (pt.lambda_destr) {
+                    if (lowerable(&pt, op)) {
                         F[i * w + j] = (int32_t)pt.alpha_minus;
                         ++lowered_this_pass;
                     }
@@ -272,9 +312,11 @@ int oracle_sweep_ordered(int32_t* F, int64_t h, int64_t w, uint32_t lambda, int3
  * the characterisations actually performed.
  */
 int oracle_sweep_dirty(int32_t* F, int64_t h, int64_t w, uint32_t lambda, int32_t adjacency,
-                       uint64_t* passes_out, uint64_t* lowerings_out, uint64_t* examinations_out)
+                       int32_t op, uint64_t* passes_out, uint64_t* lowerings_out,
+                       uint64_t* examinations_out)
 {
-    if (h < 0 || w < 0 || (adjacency != 0 && adjacency != 1)) return ORACLE_EINVAL;
+    if (h < 0 || w < 0 || (adjacency != 0 && adjacency != 1) || (op != 0 && op != 1))
+        return ORACLE_EINVAL;
     uint64_t lowerings = 0, exams = 0, passes = 0;
     if (h >= 3 && w >= 3) {
         const int64_t npix = h * w;
@@ -312,7 +354,7 @@ int oracle_sweep_dirty(int32_t* F, int64_t h, int64_t w, uint32_t lambda, int32_
                 oracle_point pt;
                 classify_at(F, w, i, j, adjacency, lambda, &pt);
                 ++exams;
-                if (!pt.lambda_destr) continue;
+                if (!lowerable(&pt, op)) continue;
                 F[idx] = (int32_t)pt.alpha_minus;
                 ++lowerings;
                 lowered_any = 1;
@@ -344,10 +386,11 @@ int oracle_sweep_dirty(int32_t* F, int64_t h, int64_t w, uint32_t lambda, int32_
 }
 
 /*
- * ORACLE-QUEUE: the sequential algorithm of section 2.2 with the type set
- * "lambda-destructible": repeatedly select a lambda-destructible point of
- * minimal value and lower it to alpha-, re-examining the eight neighbours of
- * every lowered point.  A binary min-heap keyed (F(x), i, j) holds the points
+ * ORACLE-QUEUE: the sequential algorithm of section 2.2 with operator op's
+ * type set: repeatedly select a point of the type set of minimal value and
+ * lower it to alpha-, re-examining the eight neighbours of every lowered
+ * point (every point of the type set is queued: it was queued at the start
+ * or when its 3x3 last changed, so the first one popped is a minimal one).  A binary min-heap keyed (F(x), i, j) holds the points
  * to examine; a point is never queued twice.  Only the popped point changes,
  * so the keys of queued points never go stale.  Results depend on the order
  * and are compared with the sweep by invariants only.
@@ -388,9 +431,10 @@ static heap_item heap_pop(heap_item* hp, int64_t* n)
 }
 
 int oracle_queue(int32_t* F, int64_t h, int64_t w, uint32_t lambda, int32_t adjacency,
-                 uint64_t* lowerings_out, uint64_t* pops_out)
+                 int32_t op, uint64_t* lowerings_out, uint64_t* pops_out)
 {
-    if (h < 0 || w < 0 || (adjacency != 0 && adjacency != 1)) return ORACLE_EINVAL;
+    if (h < 0 || w < 0 || (adjacency != 0 && adjacency != 1) || (op != 0 && op != 1))
+        return ORACLE_EINVAL;
     uint64_t lowerings = 0, pops = 0;
     if (h >= 3 && w >= 3) {
         const int64_t npix = h * w;
@@ -411,7 +455,7 @@ int oracle_queue(int32_t* F, int64_t h, int64_t w, uint32_t lambda, int32_t adja
             queued[idx] = 0;
             oracle_point pt;
             classify_at(F, w, i, j, adjacency, lambda, &pt);
-            if (!pt.lambda_destr) continue;
+            if (!lowerable(&pt, op)) continue;
             F[idx] = (int32_t)pt.alpha_minus;
             ++lowerings;
             for (int di = -1; di <= 1; ++di)
@@ -448,6 +492,24 @@ int oracle_count_destructible(const int32_t* F, int64_t h, int64_t w, uint32_t l
         }
     if (lambda_destr_out) *lambda_destr_out = ld;
     if (destr_out) *destr_out = d;
+    return ORACLE_OK;
+}
+
+/* Number of interior pixels of F that operator `op` would lower (a stable
+ * image has none). */
+int oracle_count_lowerable(const int32_t* F, int64_t h, int64_t w, uint32_t lambda,
+                           int32_t adjacency, int32_t op, uint64_t* count_out)
+{
+    if (h < 0 || w < 0 || (adjacency != 0 && adjacency != 1) || (op != 0 && op != 1))
+        return ORACLE_EINVAL;
+    uint64_t c = 0;
+    for (int64_t i = 1; i + 1 < h; ++i)
+        for (int64_t j = 1; j + 1 < w; ++j) {
+            oracle_point pt;
+            classify_at(F, w, i, j, adjacency, lambda, &pt);
+            c += (uint64_t)lowerable(&pt, op);
+        }
+    if (count_out) *count_out = c;
     return ORACLE_OK;
 }
 
