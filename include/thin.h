@@ -8,6 +8,8 @@
  * shared memory parallel machines" (the lambda-destructible point, the
  * lowering target alpha-, and the "repeat until stability" loop of the
  * algorithm box in section 2.2 with the type set lambda-destructible).
+ * The same loop with the algorithm box's own type set (lambda-deletable and
+ * not lambda-end) gives the lambda-skeleton (thin_skeleton, THIN_OP_SKELETON).
  *
  * Conventions shared by every call:
  *   - An image is a caller-owned DEVICE buffer of h rows by w columns,
@@ -61,6 +63,18 @@ enum {
 
 enum { THIN_U8 = 1, THIN_U16 = 2 };
 enum { THIN_ADJ_8_4 = 0, THIN_ADJ_4_8 = 1 };
+
+/* Operators (thin_image.op).  Both lower a point of their type set to
+ * alpha- until stability, with the same parity-class order (section 2.2). */
+enum {
+    THIN_OP_LEVELING = 0,   /* lambda-leveling: the lambda-destructible points */
+    THIN_OP_SKELETON = 1    /* lambda-skeleton (the algorithm box of section 2.2): the
+                               lambda-deletable points that are not lambda-end points
+                               (section 2.1: a peak, T+ = 0, is lambda-deletable when
+                               F(x) - alpha- <= lambda; an end point, with exactly one
+                               n-neighbour in the section at its own level, is lambda-end
+                               when F(x) - alpha- > lambda) */
+};
 
 /* Engines (thin_config.engine).  All produce bit-identical results. */
 enum {
@@ -119,7 +133,7 @@ typedef struct thin_image {
     int32_t dtype;         /* THIN_U8 or THIN_U16 */
     uint32_t lambda;       /* contrast parameter of the lambda-destructible test */
     int32_t adjacency;     /* THIN_ADJ_8_4 or THIN_ADJ_4_8 */
-    int32_t reserved;
+    int32_t op;            /* THIN_OP_LEVELING (0) or THIN_OP_SKELETON */
 } thin_image;
 
 /* Creates a context on cfg->device (cfg may be NULL: device 0, defaults).
@@ -134,8 +148,15 @@ int thin_create(thin_ctx** out, const thin_config* cfg);
 int thin_run(thin_ctx* ctx, void* image, int64_t h, int64_t w, int32_t dtype,
              uint32_t lambda, int32_t adjacency, thin_stats* stats);
 
-/* Same as thin_run for n independent images of any sizes, dtypes, lambdas
- * and adjacencies, processed together by one device work list.  Images must
+/* The lambda-skeleton of one image (section 2.2, the algorithm box: lower
+ * the lambda-deletable, not lambda-end points until stability; section 2.1
+ * for peaks, end points and alpha-).  Arguments, conventions, order of
+ * lowering, statistics and errors as for thin_run. */
+int thin_skeleton(thin_ctx* ctx, void* image, int64_t h, int64_t w, int32_t dtype,
+                  uint32_t lambda, int32_t adjacency, thin_stats* stats);
+
+/* Same as thin_run for n independent images of any sizes, dtypes, lambdas,
+ * adjacencies and operators, processed together by one device work list.  Images must
  * not overlap.  stats: NULL or an array of n entries.  Each image's result
  * and statistics equal those of a thin_run call on it alone. */
 int thin_run_batch(thin_ctx* ctx, const thin_image* imgs, int32_t n, thin_stats* stats);
@@ -206,13 +227,15 @@ const char* thin_last_error(const thin_ctx* ctx);
 int thin_profile(thin_ctx* ctx, thin_profile_info* out, int32_t reset);
 
 /* Host-side copy of the connectivity table the kernels use for adjacency
- * `adjacency`: for each upper-neighbour mask m (bit p set when ring
- * neighbour p has F >= F(x); ring order E, NE, N, NW, W, SW, S, SE, rows
- * growing downward), out[2m] holds bit 0 = destructible (T+ = 1 and
- * T-- = 1), bits 4..6 = T--, bits 8..10 = T+; out[2m+1] holds, in byte c,
- * the ring mask of the c-th counted lower component (c < T--).  n must be
- * at least 512.  Returns THIN_OK or THIN_EINVAL.  Needs no GPU. */
-int thin_topology_table(int32_t adjacency, uint32_t* out, int32_t n);
+ * `adjacency` and operator `op`: for each upper-neighbour mask m (bit p set
+ * when ring neighbour p has F >= F(x); ring order E, NE, N, NW, W, SW, S, SE,
+ * rows growing downward), out[2m] holds bit 0 = destructible (T+ = 1 and
+ * T-- = 1), bits 4..6 = T--, bits 8..10 = T+, and for THIN_OP_SKELETON
+ * bit 1 = peak (T+ = 0) and bit 2 = end point (exactly one n-neighbour in
+ * m); out[2m+1] holds, in byte c, the ring mask of the c-th counted lower
+ * component (c < T--).  n must be at least 512.  Returns THIN_OK or
+ * THIN_EINVAL.  Needs no GPU. */
+int thin_topology_table(int32_t adjacency, int32_t op, uint32_t* out, int32_t n);
 
 #ifdef __cplusplus
 }

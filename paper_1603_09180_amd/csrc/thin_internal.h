@@ -16,7 +16,8 @@ struct ImgDev {
     int32_t h, w;
     int32_t dtype;       // 1 = u8, 2 = u16
     uint32_t lambda;
-    int32_t adj;         // 0 = (8,4), 1 = (4,8)
+    int32_t adj;         // table: adjacency (0 = (8,4), 1 = (4,8)) + 2 * operator
+                         // (0 = lambda-leveling, 1 = lambda-skeleton)
     int32_t tiles_x;     // tile grid of this image
     int32_t tiles_y;
     int32_t tile0;       // index of its first tile in the launch's tile arrays
@@ -50,15 +51,18 @@ struct WorkList {
 };
 
 // Connectivity table entry for an upper-neighbour mask (see thin_topology_table).
-//   x: bit 0 destructible, bits 4..6 T--, bits 8..10 T+
-//   y: byte c = ring mask of the c-th counted lower component
+//   flags: bit 0 destructible, bit 1 peak and bit 2 end point (skeleton
+//          tables only), bits 4..6 T--, bits 8..10 T+
+//   comps: byte c = ring mask of the c-th counted lower component
 struct TopoEntry {
     uint32_t flags;
     uint32_t comps;
 };
 
-// Host-side generation of the 2 x 256 table (adjacency-major).
-void build_topology_table(int adjacency, TopoEntry out[256]);
+// Host-side generation of the 256 entries of one (adjacency, operator) table;
+// the device holds 4 x 256 entries, table index adjacency + 2 * operator.
+constexpr int kTables = 4;
+void build_topology_table(int adjacency, int op, TopoEntry out[256]);
 
 // Residency variants.  kVarFlags keeps the tile in LDS with a re-examination
 // flag byte per pixel, every thread checking fixed cells each step;

@@ -1,4 +1,5 @@
-// thin_kernels.hip -- gfx950 kernels of the lambda-leveling loop.
+// thin_kernels.hip -- gfx950 kernels of the lambda-leveling loop and the
+// lambda-skeleton.
 //
 // A parity step t lowers, all at once, the lambda-destructible pixels of the
 // parity class s = t mod 4 (classes (i mod 2, j mod 2) = (0,0), (0,1), (1,0),
@@ -14,6 +15,11 @@
 //   least k-1 counted lower components c have v - max_c F <= lambda, i.e.
 //   contain a pixel y with v - F(y) <= lambda;
 //   a lambda-destructible x gets F(x) := alpha- = max F over L.
+// The lambda-skeleton (section 2.2's algorithm box) lowers instead the
+// lambda-deletable points that are not lambda-end points: a peak (T+ = 0) is
+// lowered too when v - alpha- <= lambda, and an end point (one upper
+// n-neighbour) is kept when v - alpha- > lambda.  Its tables carry the peak
+// and end bits; the images' table index selects the operator.
 //
 // Kernels:
 //   k_step   one parity step per launch, straight from global memory;
@@ -53,7 +59,7 @@ __device__ __forceinline__ uint32_t upper_mask(uint32_t v, const uint32_t (&nb)[
 }
 
 // Decision and new value for one candidate with upper mask u and its table
-// entry e = lut[u] (the entries of the image's adjacency).
+// entry e = lut[u] (the entries of the image's adjacency and operator).
 __device__ __forceinline__ bool decide_entry(uint32_t v, const uint32_t (&nb)[8], uint32_t u,
                                              TopoEntry e, uint32_t lambda, uint32_t& alpha)
 {
@@ -70,17 +76,24 @@ __device__ __forceinline__ bool decide_entry(uint32_t v, const uint32_t (&nb)[8]
         const uint32_t nonzero = (((hit & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | hit) & 0x80808080u;
         lower = (uint32_t)__popc(nonzero) + 1u >= k;
     }
-    if (lower) {
+    // Skeleton tables mark peaks (bit 1) and end points (bit 2); leveling
+    // tables mark neither.  A peak is lowered when its contrast v - alpha- is
+    // at most lambda; an end point that passed the test above is kept when
+    // its contrast exceeds lambda (a lambda-end point).
+    const uint32_t pe = e.flags & 6u;
+    if (lower || pe != 0u) {
         uint32_t a = 0;
 #pragma unroll
         for (int p = 0; p < 8; ++p) a = max(a, ((u >> p) & 1u) ? 0u : nb[p]);
         alpha = a;
+        if (pe != 0u) lower = (lower || pe == 2u) && v - a <= lambda;
     }
     return lower;
 }
 
 // Decision and new value for one candidate; nb in ring order E, NE, N, NW,
-// W, SW, S, SE.  lut points at the 256 entries of the image's adjacency.
+// W, SW, S, SE.  lut points at the 256 entries of the image's adjacency and
+// operator.
 __device__ __forceinline__ bool decide(uint32_t v, const uint32_t (&nb)[8], const TopoEntry* lut,
                                        uint32_t lambda, uint32_t& alpha)
 {

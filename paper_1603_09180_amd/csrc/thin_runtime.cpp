@@ -287,12 +287,20 @@ int collect_profile(thin_ctx* ctx, size_t ev_used)
     return THIN_OK;
 }
 
+// Index of the image's connectivity table on the device (adjacency and operator).
+int32_t table_index(const thin_image& im)
+{
+    return im.adjacency + 2 * im.op;
+}
+
 int validate(thin_ctx* ctx, const thin_image& im)
 {
     if (im.h < 0 || im.w < 0) return fail(ctx, THIN_EINVAL, "negative image size");
     if (im.dtype != THIN_U8 && im.dtype != THIN_U16) return fail(ctx, THIN_EINVAL, "bad dtype %d", im.dtype);
     if (im.adjacency != THIN_ADJ_8_4 && im.adjacency != THIN_ADJ_4_8)
         return fail(ctx, THIN_EINVAL, "bad adjacency %d", im.adjacency);
+    if (im.op != THIN_OP_LEVELING && im.op != THIN_OP_SKELETON)
+        return fail(ctx, THIN_EINVAL, "bad operator %d", im.op);
     if (im.pitch_elems != 0 && im.pitch_elems < im.w) return fail(ctx, THIN_EINVAL, "pitch < w");
     if (im.h > (1 << 30) || im.w > (1 << 30)) return fail(ctx, THIN_EINVAL, "image side above 2^30");
     if (im.h * im.w > 0 && im.image == nullptr) return fail(ctx, THIN_EINVAL, "NULL image");
@@ -432,7 +440,7 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
         d.w = (int32_t)im.w;
         d.dtype = im.dtype;
         d.lambda = im.lambda;
-        d.adj = im.adjacency;
+        d.adj = table_index(im);
         d.tiles_y = (int32_t)((im.h + shape.th - 1) / shape.th);
         d.tiles_x = (int32_t)((im.w + shape.tw - 1) / shape.tw);
         d.tile0 = (int32_t)plan.tile_img.size();
@@ -643,7 +651,7 @@ int run_coop(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
         d.w = (int32_t)im.w;
         d.dtype = im.dtype;
         d.lambda = im.lambda;
-        d.adj = im.adjacency;
+        d.adj = table_index(im);
         d.tiles_y = (int32_t)((im.h + shape.th - 1) / shape.th);
         d.tiles_x = (int32_t)((im.w + shape.tw - 1) / shape.tw);
         d.tile0 = (int32_t)plan.tile_img.size();
@@ -756,7 +764,7 @@ int run_step_engine(thin_ctx* ctx, const thin_image* ims, const std::vector<int>
         d.w = (int32_t)im.w;
         d.dtype = im.dtype;
         d.lambda = im.lambda;
-        d.adj = im.adjacency;
+        d.adj = table_index(im);
         d.max_steps = max_steps;
         ImgDev* d_img = static_cast<ImgDev*>(ctx->imgs.ptr);
         ImgCnt* d_cnt = static_cast<ImgCnt*>(ctx->cnt.ptr);
@@ -991,9 +999,9 @@ int thin_create(thin_ctx** out, const thin_config* cfg)
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device) == hipSuccess &&
             cus > 0)
             ctx->num_cus = cus;
-        TopoEntry table[512];
-        thin::build_topology_table(0, table);
-        thin::build_topology_table(1, table + 256);
+        TopoEntry table[thin::kTables * 256];
+        for (int t = 0; t < thin::kTables; ++t)
+            thin::build_topology_table(t & 1, t >> 1, table + 256 * t);
         if (hipMalloc((void**)&ctx->d_lut, sizeof table) != hipSuccess) { rc = THIN_ENOMEM; break; }
         if (hipMemcpy(ctx->d_lut, table, sizeof table, hipMemcpyHostToDevice) != hipSuccess) {
             rc = THIN_EDEVICE;
@@ -1025,6 +1033,21 @@ int thin_run(thin_ctx* ctx, void* image, int64_t h, int64_t w, int32_t dtype, ui
     im.dtype = dtype;
     im.lambda = lambda;
     im.adjacency = adjacency;
+    return run_images(ctx, &im, 1, stats);
+}
+
+int thin_skeleton(thin_ctx* ctx, void* image, int64_t h, int64_t w, int32_t dtype,
+                  uint32_t lambda, int32_t adjacency, thin_stats* stats)
+{
+    thin_image im{};
+    im.image = image;
+    im.h = h;
+    im.w = w;
+    im.pitch_elems = w;
+    im.dtype = dtype;
+    im.lambda = lambda;
+    im.adjacency = adjacency;
+    im.op = THIN_OP_SKELETON;
     return run_images(ctx, &im, 1, stats);
 }
 
@@ -1097,12 +1120,13 @@ int thin_profile(thin_ctx* ctx, thin_profile_info* out, int32_t reset)
     return THIN_OK;
 }
 
-int thin_topology_table(int32_t adjacency, uint32_t* out, int32_t n)
+int thin_topology_table(int32_t adjacency, int32_t op, uint32_t* out, int32_t n)
 {
-    if ((adjacency != THIN_ADJ_8_4 && adjacency != THIN_ADJ_4_8) || !out || n < 512)
+    if ((adjacency != THIN_ADJ_8_4 && adjacency != THIN_ADJ_4_8) || !out || n < 512 ||
+        (op != THIN_OP_LEVELING && op != THIN_OP_SKELETON))
         return THIN_EINVAL;
     TopoEntry t[256];
-    thin::build_topology_table(adjacency, t);
+    thin::build_topology_table(adjacency, op, t);
     for (int m = 0; m < 256; ++m) {
         out[2 * m] = t[m].flags;
         out[2 * m + 1] = t[m].comps;
@@ -1231,7 +1255,7 @@ int thin_serve_step(thin_ctx* ctx, int32_t rounds, uint64_t* done_tags, thin_sta
                 d.w = (int32_t)r.img.w;
                 d.dtype = r.img.dtype;
                 d.lambda = r.img.lambda;
-                d.adj = r.img.adjacency;
+                d.adj = table_index(r.img);
                 d.tiles_x = r.tiles_x;
                 d.tiles_y = r.tiles_y;
                 d.tile0 = (int32_t)tile_img.size();

@@ -1,6 +1,8 @@
 // topo_table.cpp -- connectivity table of the 3x3 characterisation, generated
 // on the host from the definitions of section 2.1 (T+ = #C_n[x, Gamma+],
-// T-- = #C_n'[x, Gamma--], destructible <=> T+ = 1 and T-- = 1).
+// T-- = #C_n'[x, Gamma--], destructible <=> T+ = 1 and T-- = 1; for the
+// lambda-skeleton also peak points, T+ = 0, and end points, exactly one
+// n-neighbour in the section of the point's own level).
 //
 // The kernels index it by the upper-neighbour mask U (bit p set when ring
 // neighbour p has F >= F(x)); the lower set is L = ~U.  The ring positions
@@ -59,10 +61,11 @@ int counted_components(unsigned set, int m, unsigned masks[8])
 
 }  // namespace
 
-void build_topology_table(int adjacency, TopoEntry out[256])
+void build_topology_table(int adjacency, int op, TopoEntry out[256])
 {
     const int n = adjacency == 0 ? 8 : 4;
     const int nbar = adjacency == 0 ? 4 : 8;
+    const unsigned n_neighbours = (n == 8) ? 0xFFu : 0x55u;
     for (unsigned u = 0; u < 256; ++u) {
         unsigned up[8], lo[8];
         const int tplus = counted_components(u, n, up);
@@ -70,7 +73,13 @@ void build_topology_table(int adjacency, TopoEntry out[256])
         uint32_t comps = 0;
         for (int c = 0; c < tminus && c < 4; ++c) comps |= (uint32_t)lo[c] << (8 * c);
         const uint32_t destructible = (tplus == 1 && tminus == 1) ? 1u : 0u;
-        out[u].flags = destructible | ((uint32_t)tminus << 4) | ((uint32_t)tplus << 8);
+        uint32_t flags = destructible | ((uint32_t)tminus << 4) | ((uint32_t)tplus << 8);
+        if (op == 1) {
+            // peak: T+ = 0; end point: exactly one n-neighbour in Gamma+
+            if (tplus == 0) flags |= 2u;
+            if (__builtin_popcount(u & n_neighbours) == 1) flags |= 4u;
+        }
+        out[u].flags = flags;
         out[u].comps = comps;
     }
 }

@@ -118,6 +118,7 @@ class Job:
     kind: str = "blobs"
     sigma: object = (4.0, 16.0)
     arrival: float = 0.0          # seconds from trace start (serving only)
+    op: str = "leveling"          # "leveling" or "skeleton"
 
     def image(self) -> np.ndarray:
         if self.kind == "blobs":
@@ -139,6 +140,12 @@ def blobs_128() -> Job:
 def ridges_512() -> Job:
     """Single 512x512 u8 ridge image, lambda 20, (8,4): the paper-shaped case."""
     return Job(512, 512, U8, 20, 0, seed=2, kind="ridges")
+
+
+def skeleton_512() -> Job:
+    """The 512x512 ridge image under the lambda-skeleton with lambda 10 (the
+    value of the paper's filtered-skeleton illustration), (8,4)."""
+    return Job(512, 512, U8, 10, 0, seed=2, kind="ridges", op="skeleton")
 
 
 def blobs_8192_u16() -> Job:

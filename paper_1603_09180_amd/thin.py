@@ -1,8 +1,8 @@
 """ctypes binding of libthin.so (include/thin.h).
 
 The functions named like the C calls (thin_create, thin_run, ...) only
-marshal arguments; every step of the lambda-leveling loop runs in the HIP
-library.  torch is used for device memory and streams only.  If the library
+marshal arguments; every step of the lambda-leveling loop and of the
+lambda-skeleton runs in the HIP library.  torch is used for device memory and streams only.  If the library
 has not been built the binding raises ThinError: there is no CPU fallback.
 """
 from __future__ import annotations
@@ -17,13 +17,15 @@ LIB_PATH = os.path.join(HERE, "libthin.so")
 THIN_OK, THIN_EINVAL, THIN_ENOMEM, THIN_EDEVICE, THIN_ELIMIT, THIN_EBUSY = 0, -1, -2, -3, -4, -5
 THIN_U8, THIN_U16 = 1, 2
 THIN_ADJ_8_4, THIN_ADJ_4_8 = 0, 1
+THIN_OP_LEVELING, THIN_OP_SKELETON = 0, 1
 THIN_ENGINE_AUTO, THIN_ENGINE_TILED, THIN_ENGINE_STEP, THIN_ENGINE_PERSIST, THIN_ENGINE_COOP = (
     0, 1, 2, 3, 4)
 THIN_FLAG_PROFILE = 1
 THIN_FLAG_GRAPH = 2
 
 EXPORTED = [
-    "thin_create", "thin_run", "thin_run_batch", "thin_serve_admit", "thin_serve_step",
+    "thin_create", "thin_run", "thin_skeleton", "thin_run_batch", "thin_serve_admit",
+    "thin_serve_step",
     "thin_destroy", "thin_strerror", "thin_last_error", "thin_profile", "thin_topology_table",
     "thin_autotune",
 ]
@@ -78,7 +80,7 @@ class thin_image(ctypes.Structure):
         ("dtype", ctypes.c_int32),
         ("lambda_", ctypes.c_uint32),
         ("adjacency", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("op", ctypes.c_int32),
     ]
 
 
@@ -114,6 +116,8 @@ def load_library(path: str = LIB_PATH):
     lib.thin_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                              ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32, P(thin_stats)]
     lib.thin_run.restype = ctypes.c_int
+    lib.thin_skeleton.argtypes = lib.thin_run.argtypes
+    lib.thin_skeleton.restype = ctypes.c_int
     lib.thin_run_batch.argtypes = [ctypes.c_void_p, P(thin_image), ctypes.c_int32, P(thin_stats)]
     lib.thin_run_batch.restype = ctypes.c_int
     lib.thin_serve_admit.argtypes = [ctypes.c_void_p, P(thin_image), ctypes.c_uint64]
@@ -130,7 +134,8 @@ def load_library(path: str = LIB_PATH):
     lib.thin_last_error.restype = ctypes.c_char_p
     lib.thin_profile.argtypes = [ctypes.c_void_p, P(thin_profile_info), ctypes.c_int32]
     lib.thin_profile.restype = ctypes.c_int
-    lib.thin_topology_table.argtypes = [ctypes.c_int32, P(ctypes.c_uint32), ctypes.c_int32]
+    lib.thin_topology_table.argtypes = [ctypes.c_int32, ctypes.c_int32, P(ctypes.c_uint32),
+                                        ctypes.c_int32]
     lib.thin_topology_table.restype = ctypes.c_int
     lib.thin_autotune.argtypes = [ctypes.c_void_p, P(thin_image), ctypes.c_int32, ctypes.c_int32,
                                   P(thin_tune_result)]
@@ -156,6 +161,13 @@ def thin_run(ctx, image_ptr: int, h: int, w: int, dtype: int, lam: int, adjacenc
     return load_library().thin_run(ctx, ctypes.c_void_p(image_ptr), h, w, dtype,
                                    ctypes.c_uint32(lam), adjacency,
                                    ctypes.byref(stats) if stats is not None else None)
+
+
+def thin_skeleton(ctx, image_ptr: int, h: int, w: int, dtype: int, lam: int, adjacency: int,
+                  stats: thin_stats | None = None) -> int:
+    return load_library().thin_skeleton(ctx, ctypes.c_void_p(image_ptr), h, w, dtype,
+                                        ctypes.c_uint32(lam), adjacency,
+                                        ctypes.byref(stats) if stats is not None else None)
 
 
 def thin_run_batch(ctx, images, n: int, stats=None) -> int:
@@ -191,11 +203,11 @@ def thin_profile(ctx, reset: bool = False) -> thin_profile_info:
     return info
 
 
-def thin_topology_table(adjacency: int):
+def thin_topology_table(adjacency: int, op: int = THIN_OP_LEVELING):
     """The connectivity table the kernels use: a list of 256 (flags, comps)."""
     lib = load_library()
     buf = (ctypes.c_uint32 * 512)()
-    rc = lib.thin_topology_table(adjacency, buf, 512)
+    rc = lib.thin_topology_table(adjacency, op, buf, 512)
     if rc != THIN_OK:
         raise ThinError(rc, "thin_topology_table")
     return [(buf[2 * m], buf[2 * m + 1]) for m in range(256)]
@@ -224,6 +236,14 @@ def _adj_code(adj) -> int:
     raise ValueError(f"unknown adjacency {adj!r}")
 
 
+def _op_code(op) -> int:
+    if op in (THIN_OP_LEVELING, "leveling"):
+        return THIN_OP_LEVELING
+    if op in (THIN_OP_SKELETON, "skeleton"):
+        return THIN_OP_SKELETON
+    raise ValueError(f"unknown operator {op!r}")
+
+
 def _dtype_code(t) -> int:
     import torch
 
@@ -234,8 +254,9 @@ def _dtype_code(t) -> int:
     raise ValueError(f"unsupported dtype {t.dtype}")
 
 
-def describe(t, lam: int, adj) -> thin_image:
-    """thin_image for a 2-D uint8/uint16 CUDA tensor with unit column stride."""
+def describe(t, lam: int, adj, op="leveling") -> thin_image:
+    """thin_image for a 2-D uint8/uint16 CUDA tensor with unit column stride;
+    op is "leveling" (lambda-leveling) or "skeleton" (lambda-skeleton)."""
     if t.dim() != 2 or not t.is_cuda:
         raise ValueError("expected a 2-D tensor on the GPU")
     if t.numel() and t.stride(1) != 1:
@@ -247,6 +268,7 @@ def describe(t, lam: int, adj) -> thin_image:
     im.dtype = _dtype_code(t)
     im.lambda_ = int(lam)
     im.adjacency = _adj_code(adj)
+    im.op = _op_code(op)
     return im
 
 
@@ -303,31 +325,33 @@ class Context:
     def profile(self, reset: bool = False) -> thin_profile_info:
         return thin_profile(self.handle, reset)
 
-    def run(self, t, lam: int, adj="8,4", allow_limit: bool = False) -> Stats:
+    def run(self, t, lam: int, adj="8,4", allow_limit: bool = False, op="leveling") -> Stats:
         """Thins one device tensor in place; returns its statistics."""
-        im = describe(t, lam, adj)
+        im = describe(t, lam, adj, op)
         st = thin_stats()
         rc = load_library().thin_run_batch(self.handle, ctypes.byref(im), 1, ctypes.byref(st))
         self._check(rc, "thin_run", allow_limit)
         return Stats.of(st)
 
-    def run_batch(self, tensors, lams, adjs, allow_limit: bool = False):
+    def run_batch(self, tensors, lams, adjs, allow_limit: bool = False, ops=None):
         n = len(tensors)
+        ops = ops if ops is not None else ["leveling"] * n
         arr = (thin_image * max(n, 1))()
-        for i, (t, lam, adj) in enumerate(zip(tensors, lams, adjs)):
-            arr[i] = describe(t, lam, adj)
+        for i, (t, lam, adj, op) in enumerate(zip(tensors, lams, adjs, ops)):
+            arr[i] = describe(t, lam, adj, op)
         st = (thin_stats * max(n, 1))()
         rc = thin_run_batch(self.handle, arr, n, st)
         self._check(rc, "thin_run_batch", allow_limit)
         return [Stats.of(st[i]) for i in range(n)]
 
-    def autotune(self, tensors, lams, adjs, reps: int = 2) -> dict:
+    def autotune(self, tensors, lams, adjs, reps: int = 2, ops=None) -> dict:
         """Times every compiled tile shape on copies of these images and makes
         the fastest this context's choice for work lists of their size class."""
         n = len(tensors)
+        ops = ops if ops is not None else ["leveling"] * n
         arr = (thin_image * max(n, 1))()
-        for i, (t, lam, adj) in enumerate(zip(tensors, lams, adjs)):
-            arr[i] = describe(t, lam, adj)
+        for i, (t, lam, adj, op) in enumerate(zip(tensors, lams, adjs, ops)):
+            arr[i] = describe(t, lam, adj, op)
         res = thin_tune_result()
         rc = load_library().thin_autotune(self.handle, arr, n, reps, ctypes.byref(res))
         self._check(rc, "thin_autotune")
@@ -337,10 +361,10 @@ class Context:
 
     # ---------------------------------------------------------- serving
 
-    def serve_admit(self, t, lam: int, adj="8,4", tag: int = 0) -> bool:
+    def serve_admit(self, t, lam: int, adj="8,4", tag: int = 0, op="leveling") -> bool:
         """Makes device tensor `t` resident for serving under `tag`; False
         when the serving budget is full (nothing admitted)."""
-        im = describe(t, lam, adj)
+        im = describe(t, lam, adj, op)
         rc = thin_serve_admit(self.handle, im, tag)
         if rc == THIN_EBUSY:
             return False
@@ -361,7 +385,7 @@ class Context:
         return [(int(tags[i]), Stats.of(sts[i])) for i in range(n_done.value)], n_res.value
 
 
-def run(t, lam: int, adj="8,4", **kw) -> Stats:
+def run(t, lam: int, adj="8,4", op="leveling", **kw) -> Stats:
     """One-shot convenience: thin device tensor `t` in place."""
     with Context(device=t.device.index or 0, **kw) as ctx:
-        return ctx.run(t, lam, adj)
+        return ctx.run(t, lam, adj, op=op)

@@ -1,5 +1,6 @@
 """Writes full_size.json: the oracle's result digests for the full-size
-single-image workloads, so GPU tests can check bit-exactness at sizes where
+single-image workloads (lambda-leveling, and the lambda-skeleton of the ridge
+image), so GPU tests can check bit-exactness at sizes where
 the oracle takes about a minute.
 
 For each workload it stores the SHA-256 of the generated input (so a test
@@ -25,6 +26,7 @@ from paper_1603_09180_amd import synth  # noqa: E402
 WORKLOADS = {
     "ridges_512": synth.ridges_512,
     "blobs_8192_u16": synth.blobs_8192_u16,
+    "skeleton_512": synth.skeleton_512,
 }
 
 
@@ -38,9 +40,9 @@ def main():
     for name, make in WORKLOADS.items():
         job = make()
         F = job.image()
-        ref = oracle.sweep_dirty(F, job.lam, job.adj)
+        ref = oracle.sweep_dirty(F, job.lam, job.adj, op=job.op)
         out[name] = {"h": int(F.shape[0]), "w": int(F.shape[1]), "dtype": str(F.dtype),
-                     "lambda": int(job.lam), "adjacency": int(job.adj),
+                     "lambda": int(job.lam), "adjacency": int(job.adj), "op": job.op,
                      "input_sha256": digest(F), "output_sha256": digest(ref.image),
                      "passes": int(ref.passes), "lowerings": int(ref.lowerings)}
         print(name, out[name], flush=True)

@@ -63,15 +63,19 @@ def test_null_context_and_bad_arguments(lib):
     assert lib.thin_create(ctypes.byref(h), ctypes.byref(cfg)) == thin.THIN_EINVAL
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.thin_strerror(code)
-    assert lib.thin_topology_table(2, None, 512) == thin.THIN_EINVAL
+    assert lib.thin_topology_table(2, 0, None, 512) == thin.THIN_EINVAL
+    buf = (ctypes.c_uint32 * 512)()
+    assert lib.thin_topology_table(0, 2, buf, 512) == thin.THIN_EINVAL
+    assert lib.thin_skeleton(None, None, 4, 4, 1, 0, 0, ctypes.byref(st)) == thin.THIN_EINVAL
 
 
 OWN_RING = [(0, 1), (-1, 1), (-1, 0), (-1, -1), (0, -1), (1, -1), (1, 0), (1, 1)]
 
 
+@pytest.mark.parametrize("op", [0, 1])
 @pytest.mark.parametrize("adj", [0, 1])
-def test_table_matches_oracle_characterisation(lib, adj):
-    table = thin.thin_topology_table(adj)
+def test_table_matches_oracle_characterisation(lib, adj, op):
+    table = thin.thin_topology_table(adj, op)
     for mask in range(256):
         flags, comps = table[mask]
         # Patch: ring neighbour p is upper (200) when bit p is set, else a
@@ -82,6 +86,10 @@ def test_table_matches_oracle_characterisation(lib, adj):
             patch[1 + di, 1 + dj] = 200 if (mask >> p) & 1 else 10 + p
         pt = oracle.classify_patch(patch, adj, 0)
         assert (flags & 1) == int(pt.destructible), mask
+        # peak and end bits only in the skeleton's tables
+        assert (flags >> 1) & 1 == (int(pt.peak) if op else 0), mask
+        assert (flags >> 2) & 1 == (int(pt.end) if op else 0), mask
+        assert flags & 0xF808 == 0, mask
         assert (flags >> 4) & 7 == pt.tminus, mask
         assert (flags >> 8) & 7 == pt.tplus, mask
         masks = [(comps >> (8 * c)) & 0xFF for c in range(4)]

@@ -6,8 +6,9 @@ lowering count stored in golden/full_size.json (written by
 golden/make_full_size.py from the oracle alone).  If the input generator
 does not reproduce the stored input digest on this machine, the oracle runs
 here instead (about a minute at 8192x8192).  Properties that hold at any
-size are checked directly: no lambda-destructible point remains, values
+size are checked directly: no point of the operator's type set remains, values
 only go down, every output value is an input value, the frame is untouched.
+The lambda-skeleton of the ridge image is checked the same way.
 """
 import hashlib
 import json
@@ -37,28 +38,29 @@ def digest(a):
 
 
 @pytest.mark.parametrize("name,make", [("ridges_512", synth.ridges_512),
-                                       ("blobs_8192_u16", synth.blobs_8192_u16)])
+                                       ("blobs_8192_u16", synth.blobs_8192_u16),
+                                       ("skeleton_512", synth.skeleton_512)])
 def test_full_size(name, make):
     g = GOLDEN[name]
     job = make()
     F = job.image()
-    assert (F.shape, str(F.dtype), job.lam, job.adj) == ((g["h"], g["w"]), g["dtype"],
-                                                         g["lambda"], g["adjacency"])
+    assert (F.shape, str(F.dtype), job.lam, job.adj, job.op) == (
+        (g["h"], g["w"]), g["dtype"], g["lambda"], g["adjacency"], g["op"])
     say("case full size", name)
     t = torch.from_numpy(F).cuda()
     with thin.Context() as ctx:
-        st = ctx.run(t, job.lam, job.adj)
+        st = ctx.run(t, job.lam, job.adj, op=job.op)
     out = t.cpu().numpy()
     if digest(F) == g["input_sha256"]:
         want = (g["output_sha256"], g["passes"], g["lowerings"])
     else:
         say("input differs from the stored digest here; running the oracle")
-        ref = oracle.sweep_dirty(F, job.lam, job.adj)
+        ref = oracle.sweep_dirty(F, job.lam, job.adj, op=job.op)
         want = (digest(ref.image), ref.passes, ref.lowerings)
     assert (digest(out), st.passes, st.lowerings) == want
     assert st.converged
     # size-independent properties
-    assert oracle.count_destructible(out, job.lam, job.adj)[0] == 0
+    assert oracle.count_lowerable(out, job.lam, job.adj, op=job.op) == 0
     assert (out <= F).all()
     assert np.isin(np.unique(out), np.unique(F)).all()
     assert np.array_equal(out[0], F[0]) and np.array_equal(out[-1], F[-1])
