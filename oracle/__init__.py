@@ -1,5 +1,5 @@
-"""CPU oracle for the lambda-leveling loop and the lambda-skeleton (test
-infrastructure only).
+"""CPU oracle for the lambda-leveling loop and the lambda-skeleton, and (in
+``oracle.deriche``) for the gradient front-end (test infrastructure only).
 
 Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  The product library never calls it, and the two share no
