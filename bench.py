@@ -10,7 +10,9 @@ library works in place); the timed region brackets exactly --steps runs with
 a device synchronisation on both sides.
 
 Other workloads (--workload): blobs_128, blobs_8192_u16, skeleton_512 (the
-ridge image under the lambda-skeleton, lambda = 10), batch_512 (512
+ridge image under the lambda-skeleton, lambda = 10), gradient_skeleton_512
+(a 512x512 blob image's Deriche gradient, then its lambda-skeleton, both on
+the GPU in every step), batch_512 (512
 uneven images in one batched call, compared with 512 plain calls), serving
 (Poisson arrivals at 2000 images/s of u8/u16 images with sides 64..4096
 through the continuous-batching calls: throughput with p50/p99 latency from
@@ -83,8 +85,13 @@ def cpu_baseline(images, budget_s: float):
     px = 0
     n = 0
     while True:
-        for F, lam, adj, *op in images:
-            oracle.sweep_dirty(F, lam, adj, op=op[0] if op else "leveling")
+        for F, lam, adj, *extra in images:
+            op = extra[0] if extra else "leveling"
+            front = extra[1] if len(extra) > 1 else None
+            if front is not None:
+                from oracle import deriche
+                F = deriche.gradient_image(F, *front)
+            oracle.sweep_dirty(F, lam, adj, op=op)
             px += F.shape[0] * F.shape[1]
             n += 1
             if time.perf_counter() - t0 > budget_s:
@@ -125,14 +132,26 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, graph=False
     F = job.image()
     h, w = F.shape
     b = F.dtype.itemsize
-    ref = oracle.sweep_dirty(F, job.lam, job.adj, op=job.op)
+    front = job.front
+    if front is not None:
+        # the thinned image is the input's gradient (oracle: float32 decision)
+        from oracle import deriche
+        ref = oracle.sweep_dirty(deriche.gradient_image(F, *front), job.lam, job.adj, op=job.op)
+    else:
+        ref = oracle.sweep_dirty(F, job.lam, job.adj, op=job.op)
     src = torch.from_numpy(F).cuda()
     inputs = [src.clone() for _ in range(warmup + steps)]
     torch.cuda.synchronize()
     ctx_kw = dict(tile=tile, steps_per_round=k, engine=engine)
     ctx = thin.Context(device=0, graph=graph, **ctx_kw)
+
+    def one(c, t):
+        if front is not None:
+            c.gradient(t, t, *front)
+        return c.run(t, job.lam, job.adj, op=job.op)
+
     for i in range(warmup):
-        ctx.run(inputs[i], job.lam, job.adj, op=job.op)
+        one(ctx, inputs[i])
     torch.cuda.synchronize()
     bit_exact = bool(np.array_equal(inputs[0].cpu().numpy(), ref.image))
     # Timed region: exactly `steps` runs, no per-launch events.
@@ -142,7 +161,7 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, graph=False
     t0 = time.perf_counter()
     for i in range(steps):
         s0 = time.perf_counter()
-        stats = ctx.run(inputs[warmup + i], job.lam, job.adj, op=job.op)
+        stats = one(ctx, inputs[warmup + i])
         lat.append((time.perf_counter() - s0) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -154,8 +173,7 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, graph=False
     # Kernel durations: the same runs again on fresh copies, each round
     # kernel bracketed by HIP events on the library's stream.
     again = [src.clone() for _ in range(steps)]
-    launches, kernel_ms = _kernel_pass(ctx_kw, again, (job.lam, job.adj, job.op),
-                                       lambda c, t, lam, adj, op: c.run(t, lam, adj, op=op))
+    launches, kernel_ms = _kernel_pass(ctx_kw, again, (), one)
     launches = max(launches, 1)
     elapsed = t1 - t0
     mpx = h * w * steps / elapsed / 1e6
@@ -178,6 +196,8 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, graph=False
         "data": "synthetic",
         "config": {"workload": name, "h": h, "w": w, "lambda": job.lam,
                    "adjacency": "8,4" if job.adj == 0 else "4,8", "operator": job.op,
+                   "front_end": ({"deriche_gradient": True, "alpha": front[0], "gain": front[1]}
+                                 if front else None),
                    "images_per_step": 1,
                    "path": "plain (thin_run)", "graph": graph,
                    "engine": {0: "auto", 1: "tiled", 2: "step", 3: "persistent",
@@ -204,7 +224,7 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, graph=False
         },
     }
     if cpu_s > 0:
-        v, n, dt = cpu_baseline([(F, job.lam, job.adj, job.op)], cpu_s)
+        v, n, dt = cpu_baseline([(F, job.lam, job.adj, job.op, front)], cpu_s)
         out["cpu_baseline"] = {"value": round(v, 4), "unit": "Mpixel/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"ORACLE-SWEEP-DIRTY, single-thread C, {n} run(s) of the "
@@ -452,7 +472,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ridges_512",
                     choices=["ridges_512", "blobs_128", "blobs_8192_u16", "skeleton_512",
-                             "batch_512", "serving", "copy_calibration"])
+                             "gradient_skeleton_512", "batch_512", "serving",
+                             "copy_calibration"])
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="length of the serving trace (Poisson arrivals at 2000/s)")
     ap.add_argument("--serve-rounds", type=int, default=2,
@@ -494,7 +515,8 @@ def main():
     else:
         job = {"ridges_512": synth.ridges_512, "blobs_128": synth.blobs_128,
                "blobs_8192_u16": synth.blobs_8192_u16,
-               "skeleton_512": synth.skeleton_512}[args.workload]()
+               "skeleton_512": synth.skeleton_512,
+               "gradient_skeleton_512": synth.gradient_skeleton_512}[args.workload]()
         out = bench_single(job, args.workload, args.steps, args.warmup, args.cpu_seconds,
                            args.tile, args.k, args.engine, graph=args.graph)
     print(json.dumps(out), flush=True)

@@ -212,6 +212,33 @@ typedef struct thin_tune_result {
 int thin_autotune(thin_ctx* ctx, const thin_image* imgs, int32_t n, int32_t reps,
                   thin_tune_result* out);
 
+/* Gradient front-end: the image the paper thins in its illustration
+ * (Fig. 1(a)) is the Deriche gradient of a grayscale image.  Computes, in
+ * float32, Deriche's recursive smoothing f(n) = k (a|n| + 1) r^|n| and
+ * derivative g(n) = -c n r^|n| (r = exp(-alpha); k gives f unit sum, c gives
+ * g unit response to a unit ramp): gx = g along columns of f along rows,
+ * gy = g along rows of f along columns, with signals extended by their edge
+ * values; stores min(top, rint(sqrt(gx^2 + gy^2) * gain)) into dst (top =
+ * 255 for THIN_U8, 65535 for THIN_U16).  src and dst are caller-owned device
+ * buffers of h rows and w columns with row pitches in elements (0 = w); dst
+ * may be src itself when dtype and pitch match.  magnitude is NULL or a
+ * device buffer of h*w floats (contiguous) that receives sqrt(gx^2 + gy^2).
+ * Every float operation is rounded on its own in a fixed order, so results
+ * are reproducible bit for bit.  The context keeps 16 bytes per pixel of
+ * scratch.  Synchronous like thin_run.  Returns THIN_OK, THIN_EINVAL (bad
+ * size, dtype or pitch, alpha <= 0, gain < 0 or not finite, NULL buffer with
+ * h*w > 0), THIN_ENOMEM or THIN_EDEVICE. */
+int thin_gradient(thin_ctx* ctx, const void* src, int64_t h, int64_t w, int64_t src_pitch,
+                  int32_t src_dtype, float alpha, float gain, void* dst, int64_t dst_pitch,
+                  int32_t dst_dtype, float* magnitude);
+
+/* The 12 float32 coefficients thin_gradient uses for alpha (a0..a3 of the
+ * smoothing recursions, d1 and d2 of the derivative ones, the feedback b1 and
+ * b2, then the steady states of the causal and anticausal smoothing and
+ * derivative recursions for a constant input of 1).  n must be at least 12.
+ * Returns THIN_OK or THIN_EINVAL.  Needs no GPU. */
+int thin_gradient_coefficients(float alpha, float* out, int32_t n);
+
 /* Releases the context and all scratch it owns (NULL is accepted).
  * Never frees caller images. */
 int thin_destroy(thin_ctx* ctx);

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libthin.so")
 
-SOURCES = ["thin_kernels.hip", "thin_runtime.cpp", "topo_table.cpp"]
+SOURCES = ["thin_kernels.hip", "gradient.hip", "thin_runtime.cpp", "topo_table.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -28,8 +28,8 @@ def compile_flags():
         "-std=c++17",
         "-fPIC",
         "-Wall",
-        # packed FP32 instructions stay off (none of this code is floating point,
-        # and the compiler must not introduce them)
+        # packed FP32 instructions stay off (the compiler must not introduce
+        # them; the gradient front-end's float code runs scalar)
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", INCLUDE,
         "-I", CSRC,

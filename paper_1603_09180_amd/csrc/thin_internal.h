@@ -121,6 +121,19 @@ hipError_t launch_coop(hipStream_t stream, TileShape shape, const ImgDev* imgs, 
                        int max_rounds, int num_cus, uint32_t* hist_bits, int32_t* hist_round,
                        int kflags);
 bool tile_shape_supported(TileShape s);
+
+// Gradient front-end (gradient.hip): float32 coefficients of Deriche's
+// recursive smoothing (a0..a3) and derivative (d1, d2) filters, shared
+// feedback (b1, b2) and the steady states of the four recursions for a
+// constant input of 1 (the edge rule).
+struct GradCoef {
+    float a0, a1, a2, a3, d1, d2, b1, b2, s_plus, s_minus, d_plus, d_minus;
+};
+// Column pass then row pass on `stream`; A, B, P, Q are h*w float scratch
+// buffers; mag (nullable) receives the float magnitude, h*w contiguous.
+hipError_t launch_gradient(hipStream_t stream, const void* src, int64_t src_pitch, int src_dtype,
+                           int h, int w, float* A, float* B, float* P, float* Q, void* dst,
+                           int64_t dst_pitch, int dst_dtype, float* mag, GradCoef co, float gain);
 // Every compiled shape: writes up to cap of them to out, returns the count.
 int compiled_shapes(TileShape* out, int cap);
 int round_blocks_per_cu(TileShape s);

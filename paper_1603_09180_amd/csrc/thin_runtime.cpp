@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <climits>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -121,6 +122,7 @@ struct thin_ctx {
     TopoEntry* d_lut = nullptr;
     uint64_t allocated = 0;        // bytes of scratch currently held
     DevBuf twin, imgs, cnt, tile_img, tile_last, small, hist_bits, hist_round, wl_list, wl_meta;
+    DevBuf grad;                   // gradient front-end scratch (4 floats per pixel)
     ImgCnt* h_snap[2] = {nullptr, nullptr};   // pinned snapshots of the counters
     size_t h_snap_cap = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1072,7 +1074,7 @@ int thin_destroy(thin_ctx* ctx)
     DevBuf* bufs[] = {&ctx->twin,       &ctx->imgs,        &ctx->cnt,        &ctx->tile_img,
                       &ctx->tile_last,  &ctx->small,      &ctx->wl_list,    &ctx->wl_meta,
                       &ctx->hist_bits,  &ctx->hist_round,  &ctx->serve_twin, &ctx->serve_state,
-                      &ctx->serve_cnt,  &ctx->serve_imgs,  &ctx->serve_tile_img};
+                      &ctx->serve_cnt,  &ctx->serve_imgs,  &ctx->serve_tile_img, &ctx->grad};
     for (DevBuf* b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->d_lut) (void)hipFree(ctx->d_lut);
@@ -1117,6 +1119,75 @@ int thin_profile(thin_ctx* ctx, thin_profile_info* out, int32_t reset)
         ctx->prof_ms = 0.0;
         ctx->prof_tile_rounds = 0;
     }
+    return THIN_OK;
+}
+
+namespace {
+
+// Coefficients of the gradient front-end, computed in double from the
+// float32 alpha and rounded once to float32.
+thin::GradCoef gradient_coef(float alpha)
+{
+    const double a = alpha;
+    const double r = std::exp(-a);
+    const double k = (1.0 - r) * (1.0 - r) / (1.0 + 2.0 * a * r - r * r);
+    const double c = (1.0 - r) * (1.0 - r) * (1.0 - r) / (2.0 * r * (1.0 + r));
+    const double a0 = k, a1 = k * (a - 1.0) * r, a2 = k * (a + 1.0) * r, a3 = -k * r * r;
+    const double d1 = -c * r, d2 = c * r, b1 = 2.0 * r, b2 = -r * r;
+    const double den = 1.0 - b1 - b2;
+    thin::GradCoef co;
+    co.a0 = (float)a0;
+    co.a1 = (float)a1;
+    co.a2 = (float)a2;
+    co.a3 = (float)a3;
+    co.d1 = (float)d1;
+    co.d2 = (float)d2;
+    co.b1 = (float)b1;
+    co.b2 = (float)b2;
+    co.s_plus = (float)((a0 + a1) / den);
+    co.s_minus = (float)((a2 + a3) / den);
+    co.d_plus = (float)(d1 / den);
+    co.d_minus = (float)(d2 / den);
+    return co;
+}
+
+}  // namespace
+
+int thin_gradient_coefficients(float alpha, float* out, int32_t n)
+{
+    if (!out || n < 12 || !(alpha > 0.0f) || !std::isfinite(alpha)) return THIN_EINVAL;
+    const thin::GradCoef co = gradient_coef(alpha);
+    const float v[12] = {co.a0, co.a1, co.a2, co.a3, co.d1, co.d2,
+                         co.b1, co.b2, co.s_plus, co.s_minus, co.d_plus, co.d_minus};
+    for (int i = 0; i < 12; ++i) out[i] = v[i];
+    return THIN_OK;
+}
+
+int thin_gradient(thin_ctx* ctx, const void* src, int64_t h, int64_t w, int64_t src_pitch,
+                  int32_t src_dtype, float alpha, float gain, void* dst, int64_t dst_pitch,
+                  int32_t dst_dtype, float* magnitude)
+{
+    if (!ctx) return THIN_EINVAL;
+    if (h < 0 || w < 0) return fail(ctx, THIN_EINVAL, "negative image size");
+    if ((src_dtype != THIN_U8 && src_dtype != THIN_U16) || (dst_dtype != THIN_U8 && dst_dtype != THIN_U16))
+        return fail(ctx, THIN_EINVAL, "bad dtype");
+    if (!(alpha > 0.0f) || !std::isfinite(alpha)) return fail(ctx, THIN_EINVAL, "alpha must be positive");
+    if (!(gain >= 0.0f) || !std::isfinite(gain)) return fail(ctx, THIN_EINVAL, "gain must be finite, >= 0");
+    if (h > (1 << 30) || w > (1 << 30)) return fail(ctx, THIN_EINVAL, "image side above 2^30");
+    if (src_pitch == 0) src_pitch = w;
+    if (dst_pitch == 0) dst_pitch = w;
+    if (src_pitch < w || dst_pitch < w) return fail(ctx, THIN_EINVAL, "pitch < w");
+    if (h * w == 0) return THIN_OK;
+    if (!src || !dst) return fail(ctx, THIN_EINVAL, "NULL image");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const size_t plane = (size_t)h * (size_t)w;
+    int rc = ensure(ctx, ctx->grad, 4 * plane * sizeof(float));
+    if (rc) return rc;
+    float* base = static_cast<float*>(ctx->grad.ptr);
+    HIP_TRY(ctx, thin::launch_gradient(ctx->stream, src, src_pitch, src_dtype, (int)h, (int)w, base,
+                                       base + plane, base + 2 * plane, base + 3 * plane, dst,
+                                       dst_pitch, dst_dtype, magnitude, gradient_coef(alpha), gain));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return THIN_OK;
 }
 

@@ -119,6 +119,7 @@ class Job:
     sigma: object = (4.0, 16.0)
     arrival: float = 0.0          # seconds from trace start (serving only)
     op: str = "leveling"          # "leveling" or "skeleton"
+    front: tuple = None           # (alpha, gain): thin the image's gradient instead
 
     def image(self) -> np.ndarray:
         if self.kind == "blobs":
@@ -146,6 +147,13 @@ def skeleton_512() -> Job:
     """The 512x512 ridge image under the lambda-skeleton with lambda 10 (the
     value of the paper's filtered-skeleton illustration), (8,4)."""
     return Job(512, 512, U8, 10, 0, seed=2, kind="ridges", op="skeleton")
+
+
+def gradient_skeleton_512() -> Job:
+    """The pipeline of the paper's illustration on a synthetic gray image: the
+    512x512 u8 blob image's gradient (alpha 1, gain 12), then its
+    lambda-skeleton with lambda 10, (8,4)."""
+    return Job(512, 512, U8, 10, 0, seed=6, op="skeleton", front=(1.0, 12.0))
 
 
 def blobs_8192_u16() -> Job:

@@ -27,7 +27,7 @@ EXPORTED = [
     "thin_create", "thin_run", "thin_skeleton", "thin_run_batch", "thin_serve_admit",
     "thin_serve_step",
     "thin_destroy", "thin_strerror", "thin_last_error", "thin_profile", "thin_topology_table",
-    "thin_autotune",
+    "thin_autotune", "thin_gradient", "thin_gradient_coefficients",
 ]
 
 
@@ -140,6 +140,12 @@ def load_library(path: str = LIB_PATH):
     lib.thin_autotune.argtypes = [ctypes.c_void_p, P(thin_image), ctypes.c_int32, ctypes.c_int32,
                                   P(thin_tune_result)]
     lib.thin_autotune.restype = ctypes.c_int
+    lib.thin_gradient.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                  ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, P(ctypes.c_float)]
+    lib.thin_gradient.restype = ctypes.c_int
+    lib.thin_gradient_coefficients.argtypes = [ctypes.c_float, P(ctypes.c_float), ctypes.c_int32]
+    lib.thin_gradient_coefficients.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -211,6 +217,15 @@ def thin_topology_table(adjacency: int, op: int = THIN_OP_LEVELING):
     if rc != THIN_OK:
         raise ThinError(rc, "thin_topology_table")
     return [(buf[2 * m], buf[2 * m + 1]) for m in range(256)]
+
+
+def thin_gradient_coefficients(alpha: float):
+    """The 12 float32 coefficients thin_gradient uses (see include/thin.h)."""
+    buf = (ctypes.c_float * 12)()
+    rc = load_library().thin_gradient_coefficients(ctypes.c_float(alpha), buf, 12)
+    if rc != THIN_OK:
+        raise ThinError(rc, "thin_gradient_coefficients")
+    return [float(buf[i]) for i in range(12)]
 
 
 # ------------------------------------------------------- tensor-level helpers
@@ -358,6 +373,30 @@ class Context:
         return {"tile": (res.tile_h, res.tile_w), "steps_per_round": res.steps_per_round,
                 "threads": res.threads, "variant": res.variant, "candidates": res.candidates,
                 "ms": res.ms, "default_ms": res.default_ms}
+
+    def gradient(self, src, dst, alpha: float = 1.0, gain: float = 1.0, magnitude=None):
+        """Deriche gradient of device tensor `src` into `dst` (same shape,
+        uint8 or uint16); `magnitude`, when given, is a float32 tensor of the
+        same shape that receives the unquantised magnitude."""
+        for t in (src, dst):
+            if t.dim() != 2 or not t.is_cuda or (t.numel() and t.stride(1) != 1):
+                raise ValueError("expected 2-D GPU tensors with contiguous columns")
+        if tuple(src.shape) != tuple(dst.shape):
+            raise ValueError("src and dst shapes differ")
+        mptr = None
+        if magnitude is not None:
+            import torch
+            if (magnitude.dtype != torch.float32 or not magnitude.is_contiguous()
+                    or tuple(magnitude.shape) != tuple(src.shape) or not magnitude.is_cuda):
+                raise ValueError("magnitude must be a contiguous float32 GPU tensor of src's shape")
+            mptr = ctypes.cast(ctypes.c_void_p(magnitude.data_ptr()), ctypes.POINTER(ctypes.c_float))
+        h, w = int(src.shape[0]), int(src.shape[1])
+        rc = load_library().thin_gradient(
+            self.handle, ctypes.c_void_p(src.data_ptr() if src.numel() else None), h, w,
+            int(src.stride(0)) if src.numel() else w, _dtype_code(src), ctypes.c_float(alpha),
+            ctypes.c_float(gain), ctypes.c_void_p(dst.data_ptr() if dst.numel() else None),
+            int(dst.stride(0)) if dst.numel() else w, _dtype_code(dst), mptr)
+        self._check(rc, "thin_gradient")
 
     # ---------------------------------------------------------- serving
 

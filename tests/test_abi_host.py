@@ -110,3 +110,22 @@ def test_table_destructible_bit_is_the_yokoi_number():
             b = [((m >> p) & 1) ^ (1 if adj == thin.THIN_ADJ_8_4 else 0) for p in range(8)]
             n = sum(b[k] - b[k] * b[(k + 1) % 8] * b[(k + 2) % 8] for k in (0, 2, 4, 6))
             assert (flags & 1) == (1 if n == 1 else 0), (adj, m)
+
+
+@pytest.mark.parametrize("alpha", [0.3, 1.0, 2.5])
+def test_gradient_coefficients_match_the_oracle(lib, alpha):
+    """The library's float32 filter coefficients equal the oracle's
+    float64 ones rounded to float32 (the gradient kernels and the oracle's
+    float32 mode start from the same numbers)."""
+    from oracle import deriche
+    got = thin.thin_gradient_coefficients(alpha)
+    co = deriche.coefficients(alpha)
+    want = [float(np.float32(co[k])) for k in deriche.ORDER]
+    assert got == want
+
+
+def test_gradient_argument_checks(lib):
+    out = (ctypes.c_float * 12)()
+    assert lib.thin_gradient_coefficients(0.0, out, 12) == thin.THIN_EINVAL
+    assert lib.thin_gradient_coefficients(1.0, out, 11) == thin.THIN_EINVAL
+    assert lib.thin_gradient(None, None, 4, 4, 4, 1, 1.0, 1.0, None, 4, 1, None) == thin.THIN_EINVAL
