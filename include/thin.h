@@ -224,7 +224,7 @@ int thin_autotune(thin_ctx* ctx, const thin_image* imgs, int32_t n, int32_t reps
  * may be src itself when dtype and pitch match.  magnitude is NULL or a
  * device buffer of h*w floats (contiguous) that receives sqrt(gx^2 + gy^2).
  * Every float operation is rounded on its own in a fixed order, so results
- * are reproducible bit for bit.  The context keeps 16 bytes per pixel of
+ * are reproducible bit for bit.  The context keeps 32 bytes per pixel of
  * scratch.  Synchronous like thin_run.  Returns THIN_OK, THIN_EINVAL (bad
  * size, dtype or pitch, alpha <= 0, gain < 0 or not finite, NULL buffer with
  * h*w > 0), THIN_ENOMEM or THIN_EDEVICE. */

@@ -10,9 +10,13 @@
 // Signals are extended by their edge values: each recursion starts from the
 // steady state of that constant extension.
 //
-// One thread runs one column (coalesced across a wave) or one row.  Every
-// product and sum is rounded on its own, in the association order written
-// below (no contraction into fused multiply-adds), so the float32 result is
+// Each of the four recursions of a pass (causal and anticausal, smoothing
+// and derivative) runs in its own thread, one thread per column (coalesced
+// across a wave) or per row, writing its own plane; the row pass adds the
+// two halves of its input as it reads them, and a last elementwise pass adds
+// the halves of gx and gy and stores the result.  Every product and sum is
+// rounded on its own, in the association order written below (no
+// contraction into fused multiply-adds), so the float32 result is
 // reproducible bit for bit.
 #include "thin_internal.h"
 
@@ -61,193 +65,150 @@ __device__ __forceinline__ float deriv_anti(const GradCoef& co, float x1, float&
     return y;
 }
 
+// Loads sample n of a line: column j of the source image (column pass) or
+// row i of the sum of two scratch planes (row pass: A = A+ + A-, B = B+ + B-).
+template <typename T>
+struct ColLine {
+    const T* col;
+    int64_t pitch;
+    __device__ __forceinline__ float operator()(int n) const { return (float)col[(int64_t)n * pitch]; }
+};
+
+struct SumLine {
+    const float* u;
+    const float* v;
+    __device__ __forceinline__ float operator()(int n) const { return u[n] + v[n]; }
+};
+
+// One recursion along a line of n samples: kind 0 smoothing causal, 1
+// smoothing anticausal, 2 derivative causal, 3 derivative anticausal.
+// Output sample m goes to out[m * ostride].
+template <int KIND, typename Line>
+__device__ __forceinline__ void run_line(const GradCoef& co, const Line& x, int n,
+                                         float* __restrict__ out, int64_t ostride)
+{
+    constexpr bool causal = KIND == 0 || KIND == 2;
+    constexpr bool smooth = KIND == 0 || KIND == 1;
+    const float edge = causal ? x(0) : x(n - 1);
+    float s1 = edge * (causal ? (smooth ? co.s_plus : co.d_plus) : (smooth ? co.s_minus : co.d_minus));
+    float s2 = s1;
+    float x1 = edge, x2 = edge;   // previous inputs: x(m-1) (causal) or x(m+1), x(m+2)
+    auto step = [&](float xm, int m) {
+        float y;
+        if (causal) {
+            y = smooth ? smooth_causal(co, xm, x1, s1, s2) : deriv_causal(co, x1, s1, s2);
+            x1 = xm;
+        } else {
+            y = smooth ? smooth_anti(co, x1, x2, s1, s2) : deriv_anti(co, x1, s1, s2);
+            x2 = x1;
+            x1 = xm;
+        }
+        out[(int64_t)m * ostride] = y;
+    };
+    int done = 0;
+    for (; done + CH <= n; done += CH) {
+        float xs[CH];
+#pragma unroll
+        for (int t = 0; t < CH; ++t) xs[t] = x(causal ? done + t : n - 1 - done - t);
+#pragma unroll
+        for (int t = 0; t < CH; ++t) step(xs[t], causal ? done + t : n - 1 - done - t);
+    }
+    for (; done < n; ++done) {
+        const int m = causal ? done : n - 1 - done;
+        step(x(m), m);
+    }
+}
+
+// Column pass: blockIdx.y picks the recursion, one thread per column.
+// Planes: out + kind * plane (A+, A-, B+, B-).
 template <typename T>
 __global__ __launch_bounds__(kGradThreads) void k_grad_cols(const T* __restrict__ src,
                                                             int64_t pitch, int h, int w,
-                                                            float* __restrict__ A,
-                                                            float* __restrict__ B, GradCoef co)
+                                                            float* __restrict__ out,
+                                                            int64_t plane, GradCoef co)
 {
     const int j = blockIdx.x * kGradThreads + threadIdx.x;
     if (j >= w || h <= 0) return;
-    const T* col = src + j;
-    // causal halves: y+(i) from x(i), x(i-1), y+(i-1), y+(i-2); stored
-    const float x0 = (float)col[0];
-    float xp = x0;
-    float sa1 = co.s_plus * x0, sa2 = sa1;
-    float sb1 = co.d_plus * x0, sb2 = sb1;
-    int i = 0;
-    for (; i + CH <= h; i += CH) {
-        float xs[CH];
-#pragma unroll
-        for (int t = 0; t < CH; ++t) xs[t] = (float)col[(int64_t)(i + t) * pitch];
-#pragma unroll
-        for (int t = 0; t < CH; ++t) {
-            const int64_t o = (int64_t)(i + t) * w + j;
-            A[o] = smooth_causal(co, xs[t], xp, sa1, sa2);
-            B[o] = deriv_causal(co, xp, sb1, sb2);
-            xp = xs[t];
-        }
-    }
-    for (; i < h; ++i) {
-        const float x = (float)col[(int64_t)i * pitch];
-        const int64_t o = (int64_t)i * w + j;
-        A[o] = smooth_causal(co, x, xp, sa1, sa2);
-        B[o] = deriv_causal(co, xp, sb1, sb2);
-        xp = x;
-    }
-    // anticausal halves: y-(i) from x(i+1), x(i+2), y-(i+1), y-(i+2); added
-    const float xl = (float)col[(int64_t)(h - 1) * pitch];
-    float x1 = xl, x2 = xl;
-    sa1 = co.s_minus * xl;
-    sa2 = sa1;
-    sb1 = co.d_minus * xl;
-    sb2 = sb1;
-    i = h - 1;
-    for (; i + 1 >= CH; i -= CH) {
-        float xs[CH], as[CH], bs[CH];
-#pragma unroll
-        for (int t = 0; t < CH; ++t) {
-            const int64_t o = (int64_t)(i - t) * w + j;
-            xs[t] = (float)col[(int64_t)(i - t) * pitch];
-            as[t] = A[o];
-            bs[t] = B[o];
-        }
-#pragma unroll
-        for (int t = 0; t < CH; ++t) {
-            const int64_t o = (int64_t)(i - t) * w + j;
-            A[o] = as[t] + smooth_anti(co, x1, x2, sa1, sa2);
-            B[o] = bs[t] + deriv_anti(co, x1, sb1, sb2);
-            x2 = x1;
-            x1 = xs[t];
-        }
-    }
-    for (; i >= 0; --i) {
-        const int64_t o = (int64_t)i * w + j;
-        A[o] = A[o] + smooth_anti(co, x1, x2, sa1, sa2);
-        B[o] = B[o] + deriv_anti(co, x1, sb1, sb2);
-        x2 = x1;
-        x1 = (float)col[(int64_t)i * pitch];
+    const ColLine<T> line{src + j, pitch};
+    float* o = out + (int64_t)blockIdx.y * plane + j;
+    switch (blockIdx.y) {
+    case 0: run_line<0>(co, line, h, o, w); break;
+    case 1: run_line<1>(co, line, h, o, w); break;
+    case 2: run_line<2>(co, line, h, o, w); break;
+    default: run_line<3>(co, line, h, o, w); break;
     }
 }
 
-template <typename T>
-__device__ __forceinline__ void row_output(const GradCoef& co, float gxc, float gyc, float p,
-                                           float q, float gain, float top, T* out, float* mrow,
-                                           int j)
-{
-    const float gx = gxc + p;
-    const float gy = gyc + q;
-    const float sq = gx * gx + gy * gy;
-    const float m = sqrtf(sq);
-    if (mrow) mrow[j] = m;
-    out[j] = (T)fminf(rintf(m * gain), top);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kGradThreads) void k_grad_rows(
-    const float* __restrict__ A, const float* __restrict__ B, int h, int w,
-    float* __restrict__ P, float* __restrict__ Q, T* __restrict__ dst, int64_t dst_pitch,
-    float* __restrict__ mag, GradCoef co, float gain, float top)
+// Row pass: blockIdx.y picks gx+ (derivative causal of A), gx- (derivative
+// anticausal of A), gy+ (smoothing causal of B) or gy- (smoothing
+// anticausal of B), one thread per row.  Planes in: A+, A-, B+, B-; out:
+// gx+, gx-, gy+, gy-.
+__global__ __launch_bounds__(kGradThreads) void k_grad_rows(const float* __restrict__ in,
+                                                            int h, int w, int64_t plane,
+                                                            float* __restrict__ out, GradCoef co)
 {
     const int i = blockIdx.x * kGradThreads + threadIdx.x;
     if (i >= h || w <= 0) return;
-    const float* a = A + (int64_t)i * w;
-    const float* b = B + (int64_t)i * w;
-    float* p = P + (int64_t)i * w;
-    float* q = Q + (int64_t)i * w;
-    // anticausal halves first (gx from A through g, gy from B through f)
-    const float al = a[w - 1], bl = b[w - 1];
-    float a1 = al, a2 = al, b1 = bl, b2 = bl;
-    float gx1 = co.d_minus * al, gx2 = gx1;
-    float gy1 = co.s_minus * bl, gy2 = gy1;
-    int j = w - 1;
-    for (; j + 1 >= CH; j -= CH) {
-        float as[CH], bs[CH];
-#pragma unroll
-        for (int t = 0; t < CH; ++t) {
-            as[t] = a[j - t];
-            bs[t] = b[j - t];
-        }
-#pragma unroll
-        for (int t = 0; t < CH; ++t) {
-            p[j - t] = deriv_anti(co, a1, gx1, gx2);
-            q[j - t] = smooth_anti(co, b1, b2, gy1, gy2);
-            a2 = a1;
-            a1 = as[t];
-            b2 = b1;
-            b1 = bs[t];
-        }
+    const int k = blockIdx.y;
+    const int64_t row = (int64_t)i * w;
+    const float* u = in + (k < 2 ? 0 : 2 * plane) + row;
+    const SumLine line{u, u + plane};
+    float* o = out + (int64_t)k * plane + row;
+    switch (k) {
+    case 0: run_line<2>(co, line, w, o, 1); break;
+    case 1: run_line<3>(co, line, w, o, 1); break;
+    case 2: run_line<0>(co, line, w, o, 1); break;
+    default: run_line<1>(co, line, w, o, 1); break;
     }
-    for (; j >= 0; --j) {
-        p[j] = deriv_anti(co, a1, gx1, gx2);
-        q[j] = smooth_anti(co, b1, b2, gy1, gy2);
-        a2 = a1;
-        a1 = a[j];
-        b2 = b1;
-        b1 = b[j];
-    }
-    (void)a2;
-    // causal halves, the sum, the magnitude and the stored value
-    const float a0v = a[0], b0v = b[0];
-    float ap = a0v, bp = b0v;
-    gx1 = co.d_plus * a0v;
-    gx2 = gx1;
-    gy1 = co.s_plus * b0v;
-    gy2 = gy1;
-    T* out = dst + (int64_t)i * dst_pitch;
-    float* mrow = mag ? mag + (int64_t)i * w : nullptr;
-    j = 0;
-    for (; j + CH <= w; j += CH) {
-        float as[CH], bs[CH], ps[CH], qs[CH];
-#pragma unroll
-        for (int t = 0; t < CH; ++t) {
-            as[t] = a[j + t];
-            bs[t] = b[j + t];
-            ps[t] = p[j + t];
-            qs[t] = q[j + t];
-        }
-#pragma unroll
-        for (int t = 0; t < CH; ++t) {
-            const float gxc = deriv_causal(co, ap, gx1, gx2);
-            const float gyc = smooth_causal(co, bs[t], bp, gy1, gy2);
-            row_output(co, gxc, gyc, ps[t], qs[t], gain, top, out, mrow, j + t);
-            ap = as[t];
-            bp = bs[t];
-        }
-    }
-    for (; j < w; ++j) {
-        const float av = a[j], bv = b[j];
-        const float gxc = deriv_causal(co, ap, gx1, gx2);
-        const float gyc = smooth_causal(co, bv, bp, gy1, gy2);
-        row_output(co, gxc, gyc, p[j], q[j], gain, top, out, mrow, j);
-        ap = av;
-        bp = bv;
-    }
+}
+
+// gx = gx+ + gx-, gy = gy+ + gy-, magnitude, stored value; one thread per pixel.
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_out(const float* __restrict__ g, int h, int w,
+                                                  int64_t plane, T* __restrict__ dst,
+                                                  int64_t dst_pitch, float* __restrict__ mag,
+                                                  float gain, float top)
+{
+    const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (n >= plane) return;
+    const float gx = g[n] + g[plane + n];
+    const float gy = g[2 * plane + n] + g[3 * plane + n];
+    const float sq = gx * gx + gy * gy;
+    const float m = sqrtf(sq);
+    if (mag) mag[n] = m;
+    const int64_t i = n / w, j = n - i * w;
+    dst[i * dst_pitch + j] = (T)fminf(rintf(m * gain), top);
 }
 
 }  // namespace
 
 hipError_t launch_gradient(hipStream_t stream, const void* src, int64_t src_pitch, int src_dtype,
-                           int h, int w, float* A, float* B, float* P, float* Q, void* dst,
-                           int64_t dst_pitch, int dst_dtype, float* mag, GradCoef co, float gain)
+                           int h, int w, float* scratch, void* dst, int64_t dst_pitch,
+                           int dst_dtype, float* mag, GradCoef co, float gain)
 {
+    const int64_t plane = (int64_t)h * w;
+    float* cols = scratch;              // A+, A-, B+, B-
+    float* rows = scratch + 4 * plane;  // gx+, gx-, gy+, gy-
     const dim3 block(kGradThreads);
-    const dim3 gc((w + kGradThreads - 1) / kGradThreads);
-    const dim3 gr((h + kGradThreads - 1) / kGradThreads);
+    const dim3 gc((w + kGradThreads - 1) / kGradThreads, 4);
+    const dim3 gr((h + kGradThreads - 1) / kGradThreads, 4);
     if (src_dtype == 1)
         hipLaunchKernelGGL(k_grad_cols<uint8_t>, gc, block, 0, stream,
-                           static_cast<const uint8_t*>(src), src_pitch, h, w, A, B, co);
+                           static_cast<const uint8_t*>(src), src_pitch, h, w, cols, plane, co);
     else
         hipLaunchKernelGGL(k_grad_cols<uint16_t>, gc, block, 0, stream,
-                           static_cast<const uint16_t*>(src), src_pitch, h, w, A, B, co);
+                           static_cast<const uint16_t*>(src), src_pitch, h, w, cols, plane, co);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grad_rows, gr, block, 0, stream, cols, h, w, plane, rows, co);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const dim3 go((unsigned)((plane + 255) / 256));
     if (dst_dtype == 1)
-        hipLaunchKernelGGL(k_grad_rows<uint8_t>, gr, block, 0, stream, A, B, h, w, P, Q,
-                           static_cast<uint8_t*>(dst), dst_pitch, mag, co, gain, 255.0f);
+        hipLaunchKernelGGL(k_grad_out<uint8_t>, go, dim3(256), 0, stream, rows, h, w, plane,
+                           static_cast<uint8_t*>(dst), dst_pitch, mag, gain, 255.0f);
     else
-        hipLaunchKernelGGL(k_grad_rows<uint16_t>, gr, block, 0, stream, A, B, h, w, P, Q,
-                           static_cast<uint16_t*>(dst), dst_pitch, mag, co, gain, 65535.0f);
+        hipLaunchKernelGGL(k_grad_out<uint16_t>, go, dim3(256), 0, stream, rows, h, w, plane,
+                           static_cast<uint16_t*>(dst), dst_pitch, mag, gain, 65535.0f);
     return hipGetLastError();
 }
 

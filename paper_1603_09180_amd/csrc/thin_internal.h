@@ -129,11 +129,12 @@ bool tile_shape_supported(TileShape s);
 struct GradCoef {
     float a0, a1, a2, a3, d1, d2, b1, b2, s_plus, s_minus, d_plus, d_minus;
 };
-// Column pass then row pass on `stream`; A, B, P, Q are h*w float scratch
-// buffers; mag (nullable) receives the float magnitude, h*w contiguous.
+// Column pass, row pass and output pass on `stream`; scratch holds 8 h*w
+// float planes; mag (nullable) receives the float magnitude, h*w contiguous.
+constexpr int kGradPlanes = 8;
 hipError_t launch_gradient(hipStream_t stream, const void* src, int64_t src_pitch, int src_dtype,
-                           int h, int w, float* A, float* B, float* P, float* Q, void* dst,
-                           int64_t dst_pitch, int dst_dtype, float* mag, GradCoef co, float gain);
+                           int h, int w, float* scratch, void* dst, int64_t dst_pitch,
+                           int dst_dtype, float* mag, GradCoef co, float gain);
 // Every compiled shape: writes up to cap of them to out, returns the count.
 int compiled_shapes(TileShape* out, int cap);
 int round_blocks_per_cu(TileShape s);

@@ -122,7 +122,7 @@ struct thin_ctx {
     TopoEntry* d_lut = nullptr;
     uint64_t allocated = 0;        // bytes of scratch currently held
     DevBuf twin, imgs, cnt, tile_img, tile_last, small, hist_bits, hist_round, wl_list, wl_meta;
-    DevBuf grad;                   // gradient front-end scratch (4 floats per pixel)
+    DevBuf grad;                   // gradient front-end scratch (8 floats per pixel)
     ImgCnt* h_snap[2] = {nullptr, nullptr};   // pinned snapshots of the counters
     size_t h_snap_cap = 0;
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -1181,12 +1181,11 @@ int thin_gradient(thin_ctx* ctx, const void* src, int64_t h, int64_t w, int64_t 
     if (!src || !dst) return fail(ctx, THIN_EINVAL, "NULL image");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     const size_t plane = (size_t)h * (size_t)w;
-    int rc = ensure(ctx, ctx->grad, 4 * plane * sizeof(float));
+    int rc = ensure(ctx, ctx->grad, thin::kGradPlanes * plane * sizeof(float));
     if (rc) return rc;
-    float* base = static_cast<float*>(ctx->grad.ptr);
-    HIP_TRY(ctx, thin::launch_gradient(ctx->stream, src, src_pitch, src_dtype, (int)h, (int)w, base,
-                                       base + plane, base + 2 * plane, base + 3 * plane, dst,
-                                       dst_pitch, dst_dtype, magnitude, gradient_coef(alpha), gain));
+    HIP_TRY(ctx, thin::launch_gradient(ctx->stream, src, src_pitch, src_dtype, (int)h, (int)w,
+                                       static_cast<float*>(ctx->grad.ptr), dst, dst_pitch,
+                                       dst_dtype, magnitude, gradient_coef(alpha), gain));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return THIN_OK;
 }
