@@ -82,9 +82,13 @@ __device__ __forceinline__ bool decide_entry(uint32_t v, const uint32_t (&nb)[8]
     // its contrast exceeds lambda (a lambda-end point).
     const uint32_t pe = e.flags & 6u;
     if (lower || pe != 0u) {
-        uint32_t a = 0;
+        // max over L: the eight masked values are independent, the maxima
+        // form a tree of depth three
+        uint32_t m[8];
 #pragma unroll
-        for (int p = 0; p < 8; ++p) a = max(a, ((u >> p) & 1u) ? 0u : nb[p]);
+        for (int p = 0; p < 8; ++p) m[p] = ((u >> p) & 1u) ? 0u : nb[p];
+        const uint32_t a = max(max(max(m[0], m[1]), max(m[2], m[3])),
+                               max(max(m[4], m[5]), max(m[6], m[7])));
         alpha = a;
         if (pe != 0u) lower = (lower || pe == 2u) && v - a <= lambda;
     }
@@ -633,7 +637,7 @@ struct Tile {
         }
 
         const uint32_t lambda = d.lambda;
-        int my_count = 0;
+        int my_count = 0, my_last = -1;  // interior lowerings, last step with one
         // Each thread owns fixed positions of the candidate lattice (one in
         // four pixels, rows and columns of the step's parity): the region's
         // origin is even (tile side and halo are even), so the candidate of
@@ -681,13 +685,15 @@ struct Tile {
                     }
                 }
             }
-            // One lane per wave that lowered an interior pixel records the step.
-            if (__ballot(inner) != 0ull && (tid & 63) == 0) atomicMax(s_last, tau);
+            if (inner) my_last = tau;
             __syncthreads();
         }
 
         store(d, gy0, gx0, src, dst, s_img, tid);
-        if (my_count) atomicAdd(s_count, my_count);
+        if (my_count) {
+            atomicAdd(s_count, my_count);
+            atomicMax(s_last, my_last);
+        }
         __syncthreads();
         if constexpr (SEED) {
             if (sd != nullptr) {
@@ -829,7 +835,7 @@ struct RTile {
     template <int C>
     static __device__ __forceinline__ void full_step(Cells& q, const View& d, int ry0, int rx0,
                                                      uint16_t* s_img, int tau,
-                                                     const TopoEntry* lut, int* s_last, int tid,
+                                                     const TopoEntry* lut, int& my_last,
                                                      int& my_count)
     {
         // Exact region after tau steps, clipped to the image interior.
@@ -837,8 +843,7 @@ struct RTile {
         const int c_lo = max(tau + 1, 1 - rx0), c_hi = min(RW - 2 - tau, d.w - 2 - rx0);
         bool inner = false;
         step<C>(q, s_img, tau, r_lo, r_hi, c_lo, c_hi, lut, d.lambda, my_count, inner);
-        // One lane per wave that lowered an interior pixel records the step.
-        if (__ballot(inner) != 0ull && (tid & 63) == 0) atomicMax(s_last, tau);
+        if (inner) my_last = tau;
         __syncthreads();
     }
 
@@ -878,16 +883,19 @@ struct RTile {
         }
         __syncthreads();
 
-        int my_count = 0;
+        int my_count = 0, my_last = -1;  // interior lowerings, last step with one
         for (int tau = 0; tau < nsteps; tau += 4) {
-            full_step<0>(q, d, ry0, rx0, s_img, tau, lut, s_last, tid, my_count);
-            if (tau + 1 < nsteps) full_step<1>(q, d, ry0, rx0, s_img, tau + 1, lut, s_last, tid, my_count);
-            if (tau + 2 < nsteps) full_step<2>(q, d, ry0, rx0, s_img, tau + 2, lut, s_last, tid, my_count);
-            if (tau + 3 < nsteps) full_step<3>(q, d, ry0, rx0, s_img, tau + 3, lut, s_last, tid, my_count);
+            full_step<0>(q, d, ry0, rx0, s_img, tau, lut, my_last, my_count);
+            if (tau + 1 < nsteps) full_step<1>(q, d, ry0, rx0, s_img, tau + 1, lut, my_last, my_count);
+            if (tau + 2 < nsteps) full_step<2>(q, d, ry0, rx0, s_img, tau + 2, lut, my_last, my_count);
+            if (tau + 3 < nsteps) full_step<3>(q, d, ry0, rx0, s_img, tau + 3, lut, my_last, my_count);
         }
 
         store(d, gy0, gx0, src, dst, s_img, tid);
-        if (my_count) atomicAdd(s_count, my_count);
+        if (my_count) {
+            atomicAdd(s_count, my_count);
+            atomicMax(s_last, my_last);
+        }
         __syncthreads();
         last_tau = *s_last;
         return *s_count;
@@ -1068,7 +1076,7 @@ struct BTile {
         const int wave = tid >> 6, lane = tid & 63;
         const int myw = lane < WAVE_WORDS ? wave * WAVE_WORDS + lane : CLASS_WORDS;  // its word
         const int wa = myw / LWW, wj = myw - (myw / LWW) * LWW;
-        int my_count = 0;
+        int my_count = 0, my_last = -1;  // interior lowerings, last step with one
         for (int tau = 0; tau < nsteps; ++tau) {
             const int c = tau & 3, si = c >> 1, sj = c & 1;
             // Exact region after tau steps, clipped to the image interior,
@@ -1162,13 +1170,15 @@ struct BTile {
                     }
                 }
             }
-            // One lane per wave that lowered an interior pixel records the step.
-            if (__ballot(inner) != 0ull && lane == 0) atomicMax(s_last, tau);
+            if (inner) my_last = tau;
             __syncthreads();
         }
 
         store(d, gy0, gx0, src, dst, s_img, tid);
-        if (my_count) atomicAdd(s_count, my_count);
+        if (my_count) {
+            atomicAdd(s_count, my_count);
+            atomicMax(s_last, my_last);
+        }
         __syncthreads();
         if constexpr (SEED) {
             if (sd != nullptr) {
