@@ -316,3 +316,26 @@ def test_work_lists_match_full_scans(shape, monkeypatch):
             assert (st.passes, st.lowerings) == (sts[i].passes, sts[i].lowerings), i
     for i in range(0, len(Fs), 15):
         assert_same(Fs[i], lams[i], adjs[i], batch[i].cpu().numpy(), sts[i])
+
+
+def test_c_thin_run_entry_point():
+    """thin_run itself (Context.run goes through thin_run_batch)."""
+    F = synth.gen_blobs(97, 131, 4242, np.uint16, nblobs=8, sigma=(2.0, 9.0))
+    t = torch.from_numpy(F.copy()).cuda()
+    st = thin.thin_stats()
+    say("case thin_run entry")
+    with thin.Context() as ctx:
+        torch.cuda.synchronize()
+        rc = thin.thin_run(ctx.handle, t.data_ptr(), F.shape[0], F.shape[1], thin.THIN_U16,
+                           300, thin.THIN_ADJ_4_8, st)
+        assert rc == thin.THIN_OK
+    assert_same(F, 300, 1, t.cpu().numpy(), thin.Stats.of(st))
+
+
+@pytest.mark.parametrize("shape", [(3, 70001), (70001, 3), (5, 40003), (40003, 4), (2049, 7)])
+def test_extreme_aspect_ratios(shape):
+    rng = np.random.default_rng(shape[0] * 7 + shape[1])
+    F = rng.integers(0, 40, size=shape).astype(np.uint8)
+    say("case aspect", shape)
+    got, st = gpu_thin(F, 5, 0)
+    assert_same(F, 5, 0, got, st)
