@@ -54,7 +54,7 @@ struct WorkList {
 //   flags: bit 0 destructible, bit 1 peak and bit 2 end point (skeleton
 //          tables only), bits 4..6 T--, bits 8..10 T+
 //   comps: byte c = ring mask of the c-th counted lower component
-struct TopoEntry {
+struct alignas(8) TopoEntry {  // 8-byte aligned: one 64-bit load per lookup
     uint32_t flags;
     uint32_t comps;
 };

@@ -102,7 +102,12 @@ __device__ __forceinline__ bool decide(uint32_t v, const uint32_t (&nb)[8], cons
                                        uint32_t lambda, uint32_t& alpha)
 {
     const uint32_t u = upper_mask(v, nb);
-    return decide_entry(v, nb, u, lut[u], lambda, alpha);
+    // both words in one 64-bit load, so the lambda test waits for no second read
+    const uint64_t raw = reinterpret_cast<const uint64_t*>(lut)[u];
+    TopoEntry e;
+    e.flags = (uint32_t)raw;
+    e.comps = (uint32_t)(raw >> 32);
+    return decide_entry(v, nb, u, e, lambda, alpha);
 }
 
 __device__ __forceinline__ uint32_t load_px(const void* base, int dtype, int64_t idx)
