@@ -10,6 +10,9 @@
  * algorithm box in section 2.2 with the type set lambda-destructible).
  * The same loop with the algorithm box's own type set (lambda-deletable and
  * not lambda-end) gives the lambda-skeleton (thin_skeleton, THIN_OP_SKELETON).
+ * thin_gradient computes the gradient image the paper thins in its Fig. 1
+ * (a Deriche gradient magnitude), so the whole illustrated pipeline runs on
+ * the GPU.
  *
  * Conventions shared by every call:
  *   - An image is a caller-owned DEVICE buffer of h rows by w columns,
@@ -54,7 +57,8 @@ extern "C" {
 
 enum {
     THIN_OK = 0,
-    THIN_EINVAL = -1,   /* NULL pointer with h*w > 0, negative size, bad dtype or adjacency, pitch < w */
+    THIN_EINVAL = -1,   /* NULL pointer with h*w > 0, negative size, bad dtype, adjacency or
+                           operator, pitch < w */
     THIN_ENOMEM = -2,   /* scratch above max_device_bytes, or a device allocation failed */
     THIN_EDEVICE = -3,  /* a HIP call failed */
     THIN_ELIMIT = -4,   /* max_passes reached before stability */

@@ -1169,10 +1169,13 @@ int thin_gradient(thin_ctx* ctx, const void* src, int64_t h, int64_t w, int64_t 
 {
     if (!ctx) return THIN_EINVAL;
     if (h < 0 || w < 0) return fail(ctx, THIN_EINVAL, "negative image size");
-    if ((src_dtype != THIN_U8 && src_dtype != THIN_U16) || (dst_dtype != THIN_U8 && dst_dtype != THIN_U16))
+    if ((src_dtype != THIN_U8 && src_dtype != THIN_U16) ||
+        (dst_dtype != THIN_U8 && dst_dtype != THIN_U16))
         return fail(ctx, THIN_EINVAL, "bad dtype");
-    if (!(alpha > 0.0f) || !std::isfinite(alpha)) return fail(ctx, THIN_EINVAL, "alpha must be positive");
-    if (!(gain >= 0.0f) || !std::isfinite(gain)) return fail(ctx, THIN_EINVAL, "gain must be finite, >= 0");
+    if (!(alpha > 0.0f) || !std::isfinite(alpha))
+        return fail(ctx, THIN_EINVAL, "alpha must be positive and finite");
+    if (!(gain >= 0.0f) || !std::isfinite(gain))
+        return fail(ctx, THIN_EINVAL, "gain must be finite and >= 0");
     if (h > (1 << 30) || w > (1 << 30)) return fail(ctx, THIN_EINVAL, "image side above 2^30");
     if (src_pitch == 0) src_pitch = w;
     if (dst_pitch == 0) dst_pitch = w;
