@@ -219,7 +219,6 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, graph=False
             "launches_per_step": round(launches / steps, 2),
             "avg_launch_us": round(kernel_ms * 1e3 / launches, 3),
             "alg_bytes_per_launch": round(alg_bytes / launches, 1),
-            "kernel_time_frac_of_step": round(kernel_s / elapsed, 4),
             "timing": "kernel durations from HIP events in a second pass over the same runs",
         },
     }
