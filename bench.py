@@ -216,11 +216,17 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, graph=False
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
             "traffic": traffic,
+            "traffic_GBps": (round(traffic / (kernel_ms * 1e-3 / launches) / 1e9, 2)
+                             if traffic else None),
             "launches_per_step": round(launches / steps, 2),
             "avg_launch_us": round(kernel_ms * 1e3 / launches, 3),
             "alg_bytes_per_launch": round(alg_bytes / launches, 1),
             "timing": "kernel durations from HIP events in a second pass over the same runs",
         },
+        # the method's own work (oracle dirty-pixel sweep): examinations X
+        # against the streaming H*W*P pixel-passes
+        "method_work": {"examinations": int(ref.examinations), "pixel_passes": h * w * ref.passes,
+                        "fraction": round(ref.examinations / max(h * w * ref.passes, 1), 4)},
     }
     if cpu_s > 0:
         v, n, dt = cpu_baseline([(F, job.lam, job.adj, job.op, front)], cpu_s)
