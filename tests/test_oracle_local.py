@@ -240,3 +240,41 @@ def test_lambda_monotone(adj):
             cur = oracle.classify_patch(p, adj, lam).lambda_destructible
             assert cur or not prev
             prev = cur
+
+
+@pytest.mark.parametrize("adj", ["8,4", "4,8"])
+def test_connectivity_numbers_by_labelling(adj):
+    """T+ and T-- of every upper mask against scipy's labelling of the 3x3
+    neighbourhood (components of the ring subset under n or n', counted when
+    they hold a pixel n- or n'-adjacent to the centre; the centre itself
+    belongs to neither set), a method independent of the oracle's ring
+    flood fill.  The destructible masks are also counted: 116 per pairing."""
+    from scipy import ndimage
+    s8 = np.ones((3, 3), bool)
+    s4 = np.array([[0, 1, 0], [1, 1, 1], [0, 1, 0]], bool)
+    sn, sbar = (s8, s4) if adj == "8,4" else (s4, s8)
+    near = {"n": sn.copy(), "nbar": sbar.copy()}
+    for k in near.values():
+        k[1, 1] = False
+    ring = [(0, 1), (-1, 1), (-1, 0), (-1, -1), (0, -1), (1, -1), (1, 0), (1, 1)]
+    n_destr = 0
+    for u in range(256):
+        upper = np.zeros((3, 3), bool)
+        for p, (di, dj) in enumerate(ring):
+            upper[1 + di, 1 + dj] = bool((u >> p) & 1)
+        lower = ~upper
+        lower[1, 1] = False
+
+        def counted(mask, struct, touch):
+            lab, n = ndimage.label(mask, structure=struct)
+            return len({int(lab[i, j]) for i in range(3) for j in range(3)
+                        if touch[i, j] and lab[i, j] > 0})
+
+        tplus = counted(upper, sn, near["n"])
+        tminus = counted(lower, sbar, near["nbar"])
+        patch = np.where(upper, 9, 1)
+        patch[1, 1] = 5
+        pt = oracle.classify_patch(patch, adj, 0)
+        assert (pt.tplus, pt.tminus) == (tplus, tminus), u
+        n_destr += tplus == 1 and tminus == 1
+    assert n_destr == 116
