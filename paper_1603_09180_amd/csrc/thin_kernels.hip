@@ -63,35 +63,34 @@ __device__ __forceinline__ uint32_t upper_mask(uint32_t v, const uint32_t (&nb)[
 __device__ __forceinline__ bool decide_entry(uint32_t v, const uint32_t (&nb)[8], uint32_t u,
                                              TopoEntry e, uint32_t lambda, uint32_t& alpha)
 {
-    bool lower = (e.flags & 1u) != 0u;
+    // Straight-line code: inside a wave both sides of a data-dependent
+    // branch usually run anyway, so every term is computed and selected.
     const uint32_t k = (e.flags >> 4) & 7u;  // T--
-    if (!lower && lambda != 0u && k >= 2u) {
-        // lower neighbours y with v - F(y) <= lambda, i.e. F(y) >= v - lambda
-        const uint32_t floor_v = v > lambda ? v - lambda : 0u;
-        uint32_t q = 0;
+    // lower neighbours y with v - F(y) <= lambda, i.e. F(y) >= v - lambda
+    const uint32_t floor_v = v > lambda ? v - lambda : 0u;
+    uint32_t q = 0;
 #pragma unroll
-        for (int p = 0; p < 8; ++p) q |= (uint32_t)(nb[p] >= floor_v) << p;
-        q &= ~u;
-        const uint32_t hit = e.comps & (q * 0x01010101u);
-        const uint32_t nonzero = (((hit & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | hit) & 0x80808080u;
-        lower = (uint32_t)__popc(nonzero) + 1u >= k;
-    }
+    for (int p = 0; p < 8; ++p) q |= (uint32_t)(nb[p] >= floor_v) << p;
+    q &= ~u;
+    const uint32_t hit = e.comps & (q * 0x01010101u);
+    const uint32_t nonzero = (((hit & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | hit) & 0x80808080u;
+    const bool divergent_ok = lambda != 0u && k >= 2u && (uint32_t)__popc(nonzero) + 1u >= k;
+    bool lower = (e.flags & 1u) != 0u || divergent_ok;
+    // max over L: the eight masked values are independent, the maxima form
+    // a tree of depth three
+    uint32_t m[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) m[p] = ((u >> p) & 1u) ? 0u : nb[p];
+    const uint32_t a = max(max(max(m[0], m[1]), max(m[2], m[3])),
+                           max(max(m[4], m[5]), max(m[6], m[7])));
     // Skeleton tables mark peaks (bit 1) and end points (bit 2); leveling
     // tables mark neither.  A peak is lowered when its contrast v - alpha- is
     // at most lambda; an end point that passed the test above is kept when
     // its contrast exceeds lambda (a lambda-end point).
     const uint32_t pe = e.flags & 6u;
-    if (lower || pe != 0u) {
-        // max over L: the eight masked values are independent, the maxima
-        // form a tree of depth three
-        uint32_t m[8];
-#pragma unroll
-        for (int p = 0; p < 8; ++p) m[p] = ((u >> p) & 1u) ? 0u : nb[p];
-        const uint32_t a = max(max(max(m[0], m[1]), max(m[2], m[3])),
-                               max(max(m[4], m[5]), max(m[6], m[7])));
-        alpha = a;
-        if (pe != 0u) lower = (lower || pe == 2u) && v - a <= lambda;
-    }
+    const bool small = v - a <= lambda;
+    lower = pe == 0u ? lower : ((lower || pe == 2u) && small);
+    alpha = a;
     return lower;
 }
 
