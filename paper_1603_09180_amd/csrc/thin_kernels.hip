@@ -60,11 +60,49 @@ __device__ __forceinline__ uint32_t upper_mask(uint32_t v, const uint32_t (&nb)[
 
 // Decision and new value for one candidate with upper mask u and its table
 // entry e = lut[u] (the entries of the image's adjacency and operator).
-__device__ __forceinline__ bool decide_entry(uint32_t v, const uint32_t (&nb)[8], uint32_t u,
-                                             TopoEntry e, uint32_t lambda, uint32_t& alpha)
+__device__ __forceinline__ bool decide_entry_branchy(uint32_t v, const uint32_t (&nb)[8],
+                                                     uint32_t u, TopoEntry e, uint32_t lambda,
+                                                     uint32_t& alpha)
 {
-    // Straight-line code: inside a wave both sides of a data-dependent
-    // branch usually run anyway, so every term is computed and selected.
+    bool lower = (e.flags & 1u) != 0u;
+    const uint32_t k = (e.flags >> 4) & 7u;  // T--
+    if (!lower && lambda != 0u && k >= 2u) {
+        // lower neighbours y with v - F(y) <= lambda, i.e. F(y) >= v - lambda
+        const uint32_t floor_v = v > lambda ? v - lambda : 0u;
+        uint32_t q = 0;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) q |= (uint32_t)(nb[p] >= floor_v) << p;
+        q &= ~u;
+        const uint32_t hit = e.comps & (q * 0x01010101u);
+        const uint32_t nonzero = (((hit & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | hit) & 0x80808080u;
+        lower = (uint32_t)__popc(nonzero) + 1u >= k;
+    }
+    // Skeleton tables mark peaks (bit 1) and end points (bit 2); leveling
+    // tables mark neither.  A peak is lowered when its contrast v - alpha- is
+    // at most lambda; an end point that passed the test above is kept when
+    // its contrast exceeds lambda (a lambda-end point).
+    const uint32_t pe = e.flags & 6u;
+    if (lower || pe != 0u) {
+        // max over L: the eight masked values are independent, the maxima
+        // form a tree of depth three
+        uint32_t m[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) m[p] = ((u >> p) & 1u) ? 0u : nb[p];
+        const uint32_t a = max(max(max(m[0], m[1]), max(m[2], m[3])),
+                               max(max(m[4], m[5]), max(m[6], m[7])));
+        alpha = a;
+        if (pe != 0u) lower = (lower || pe == 2u) && v - a <= lambda;
+    }
+    return lower;
+}
+
+// The same decision in straight-line form.
+__device__ __forceinline__ bool decide_entry_straight(uint32_t v, const uint32_t (&nb)[8],
+                                                      uint32_t u, TopoEntry e, uint32_t lambda,
+                                                      uint32_t& alpha)
+{
+    // Straight-line form: every term is computed and selected (inside a
+    // wave both sides of a data-dependent branch usually run anyway).
     const uint32_t k = (e.flags >> 4) & 7u;  // T--
     // lower neighbours y with v - F(y) <= lambda, i.e. F(y) >= v - lambda
     const uint32_t floor_v = v > lambda ? v - lambda : 0u;
@@ -96,7 +134,10 @@ __device__ __forceinline__ bool decide_entry(uint32_t v, const uint32_t (&nb)[8]
 
 // Decision and new value for one candidate; nb in ring order E, NE, N, NW,
 // W, SW, S, SE.  lut points at the 256 entries of the image's adjacency and
-// operator.
+// operator.  STRAIGHT selects the straight-line form (measured faster where
+// whole waves examine candidates together: the register-window and bit-flag
+// residencies) over the branching one (faster for the flag residencies).
+template <bool STRAIGHT>
 __device__ __forceinline__ bool decide(uint32_t v, const uint32_t (&nb)[8], const TopoEntry* lut,
                                        uint32_t lambda, uint32_t& alpha)
 {
@@ -106,7 +147,8 @@ __device__ __forceinline__ bool decide(uint32_t v, const uint32_t (&nb)[8], cons
     TopoEntry e;
     e.flags = (uint32_t)raw;
     e.comps = (uint32_t)(raw >> 32);
-    return decide_entry(v, nb, u, e, lambda, alpha);
+    return STRAIGHT ? decide_entry_straight(v, nb, u, e, lambda, alpha)
+                    : decide_entry_branchy(v, nb, u, e, lambda, alpha);
 }
 
 __device__ __forceinline__ uint32_t load_px(const void* base, int dtype, int64_t idx)
@@ -167,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void k_step(const ImgDev* __restrict__ im
         const uint32_t nb[8] = {px[1], px[-P + 1], px[-P], px[-P - 1],
                                 px[-1], px[P - 1], px[P], px[P + 1]};
         uint32_t alpha;
-        if (decide(v, nb, s_lut, d.lambda, alpha)) {
+        if (decide<false>(v, nb, s_lut, d.lambda, alpha)) {
             px[0] = (T)alpha;
             lowered = true;
         }
@@ -670,7 +712,7 @@ struct Tile {
                     const uint32_t nbv[8] = {p[1], p[-RWP + 1], p[-RWP], p[-RWP - 1],
                                              p[-1], p[RWP - 1], p[RWP], p[RWP + 1]};
                     uint32_t alpha;
-                    if (decide(v, nbv, lut, lambda, alpha)) {
+                    if (decide<false>(v, nbv, lut, lambda, alpha)) {
                         p[0] = (uint16_t)alpha;
                         uint8_t* q = s_dirty + o;
                         q[-RWP - 1] = 1; q[-RWP] = 1; q[-RWP + 1] = 1;
@@ -824,7 +866,7 @@ struct RTile {
                                     w[4 * ci + cj - 1],       w[4 * (ci + 1) + cj - 1],
                                     w[4 * (ci + 1) + cj],     w[4 * (ci + 1) + cj + 1]};
             uint32_t alpha;
-            if (decide(w[4 * ci + cj], nb, lut, lambda, alpha)) {
+            if (decide<true>(w[4 * ci + cj], nb, lut, lambda, alpha)) {
                 w[4 * ci + cj] = alpha;
                 s_img[q.base[k] + ci * RWP + cj] = (uint16_t)alpha;
                 q.pend[k] = 0xFu;
@@ -1159,7 +1201,7 @@ struct BTile {
                 const uint32_t nbv[8] = {p[1], p[-RWP + 1], p[-RWP], p[-RWP - 1],
                                          p[-1], p[RWP - 1], p[RWP], p[RWP + 1]};
                 uint32_t alpha;
-                if (decide(v, nbv, lut, lambda, alpha)) {
+                if (decide<true>(v, nbv, lut, lambda, alpha)) {
                     p[0] = (E)alpha;
                     atomicOr(&s_dl[c * CLASS_WORDS + a * LWW + (b >> 5)], 1u << (b & 31));
                     if (lr >= K && lr < K + TH && lc >= K && lc < K + TW) {
