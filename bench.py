@@ -499,9 +499,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}, "
-              f"WORLD_SIZE={world}); images would shard across GPUs with no exchange, "
-              "but no multi-GPU figure is measured here.", file=sys.stderr)
+        print(f"bench.py: the library measures one GPU only (asked for --gpus {args.gpus}, "
+              f"WORLD_SIZE={world}); batches and served images would shard across GPUs by image "
+              "with no exchange, but no multi-GPU figure is measured.", file=sys.stderr)
         sys.exit(2)
 
     _ensure_built()
