@@ -307,8 +307,11 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512, tune=True
     small = [i for i in range(n_images) if Fs[i].size <= 300_000]
     sample = sorted(set(order[:12]) | set(small[::16]))
     exact = True
+    sample_exams = sample_passes = 0
     for i in sample:
         ref = oracle.sweep_dirty(Fs[i], lams[i], adjs[i])
+        sample_exams += int(ref.examinations)
+        sample_passes += Fs[i].size * int(ref.passes)
         got = sets[warmup + steps - 1][i].cpu().numpy()
         exact &= bool(np.array_equal(got, ref.image))
         exact &= (stats[i].passes, stats[i].lowerings) == (ref.passes, ref.lowerings)
@@ -351,6 +354,10 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512, tune=True
             "alg_bytes_per_launch": round(alg_one / max(launches, 1), 1),
             "timing": "kernel durations from HIP events in a second pass over the same batch",
         },
+        # the method's own work on the oracle-checked sample (dirty-pixel sweep)
+        "method_work": {"images": len(sample), "examinations": sample_exams,
+                        "pixel_passes": sample_passes,
+                        "fraction": round(sample_exams / max(sample_passes, 1), 4)},
     }
     if cpu_s > 0:
         smalls = [(Fs[i], lams[i], adjs[i]) for i in order[: n_images // 2]]
