@@ -254,20 +254,103 @@ def copy_calibration(nbytes=1 << 28, reps=20):
             "GBps": round(2 * nbytes * reps / dt / 1e9, 1)}
 
 
-def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512, tune=True, graph=False,
-                plain_leg=True):
-    import numpy as np
-    import torch
+def _host_cpu():
+    """CPU model name and logical CPU count of this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
 
+
+def _oracle_one(args):
+    """One oracle run in a worker process (numpy image, lambda, adjacency, plain?)."""
     import oracle
-    from paper_1603_09180_amd import synth, thin
+    F, lam, adj, plain = args
+    t0 = time.perf_counter()
+    (oracle.sweep if plain else oracle.sweep_dirty)(F, lam, adj)
+    return time.perf_counter() - t0
 
-    jobs = synth.batch_512_uneven(n_images)
+
+def pool_baseline(images, workers: int, reps: int, plain: bool):
+    """Wall time of the oracle over `images` with a fork process pool of
+    `workers` (one image per task), repeated `reps` times: (min s, median s,
+    summed single-image CPU seconds of the first repetition)."""
+    import multiprocessing as mp
+    import statistics
+    ctx = mp.get_context("fork")
+    walls, cpu = [], None
+    with ctx.Pool(workers) as pool:
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            per = pool.map(_oracle_one, [(F, lam, adj, plain) for F, lam, adj in images],
+                           chunksize=1)
+            walls.append(time.perf_counter() - t0)
+            if cpu is None:
+                cpu = sum(per)
+    return min(walls), statistics.median(walls), cpu
+
+
+def _digest(a):
+    import hashlib
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, tune=True, graph=False,
+                plain_leg=True):
+    """The 512-image batch: one thin_run_batch call per step against 512 plain
+    thin_run calls, every image of both checked bit for bit against the
+    oracle's stored digests (tests/golden/batch_512.json, written by
+    tests/golden/make_batch_512.py from the generators and the oracle)."""
+    import numpy as np
+
+    from paper_1603_09180_amd import synth
+
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "batch_512.json")))["images"]
+    jobs = synth.batch_512_uneven(len(golden))
+    n_images = len(jobs)
     Fs = [j.image() for j in jobs]
-    total_px = sum(F.size for F in Fs)
-    srcs = [torch.from_numpy(F).cuda() for F in Fs]
     lams = [j.lam for j in jobs]
     adjs = [j.adj for j in jobs]
+    total_px = sum(F.size for F in Fs)
+    same_input = [_digest(F) == g["input_sha256"] for F, g in zip(Fs, golden)]
+
+    # CPU oracle first (before the GPU is touched, so the pool forks a
+    # process without a GPU context): a bounded sample of the batch, every
+    # 32nd image, with one worker per core of the host's share.
+    cpu = None
+    if cpu_s > 0:
+        sample = list(range(0, n_images, 32))
+        imgs = [(Fs[i], lams[i], adjs[i]) for i in sample]
+        sample_px = sum(Fs[i].size for i in sample)
+        model, ncpu = _host_cpu()
+        workers = max(1, min(16, ncpu or 1, len(sample)))
+        dmin, dmed, dcpu = pool_baseline(imgs, workers, 5, plain=False)
+        pmin, pmed, pcpu = pool_baseline(imgs, workers, 1, plain=True)
+        cpu = {"value": round(sample_px / dmin / 1e6, 4), "unit": "Mpixel/s", "cores": workers,
+               "kind": "oracle",
+               "sample": (f"ORACLE-SWEEP-DIRTY on every 32nd image of the batch ({len(sample)} "
+                          f"images, {sample_px / 1e6:.2f} Mpixel), one image per task on a "
+                          f"process pool of {workers} workers; min of 5 runs"),
+               "images_per_s": round(len(sample) / dmin, 2),
+               "median_mpixel_per_s": round(sample_px / dmed / 1e6, 4),
+               "single_core_mpixel_per_s": round(sample_px / dcpu / 1e6, 4),
+               "plain_sweep": {"mpixel_per_s": round(sample_px / pmin / 1e6, 4),
+                               "single_core_mpixel_per_s": round(sample_px / pcpu / 1e6, 4),
+                               "sample": "ORACLE-SWEEP (no dirty-pixel skipping), same images "
+                                         "and pool, one run"},
+               "host_cpu": model, "host_logical_cpus": ncpu}
+
+    import torch
+    from paper_1603_09180_amd import thin
+
+    srcs = [torch.from_numpy(F).cuda() for F in Fs]
     ctx_kw = dict(tile=tile, steps_per_round=k, engine=engine)
     ctx = thin.Context(device=0, graph=graph, **ctx_kw)
     tuned = None
@@ -280,47 +363,67 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512, tune=True
     for i in range(warmup):
         ctx.run_batch(sets[i], lams, adjs)
     torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev0.record(stream)
     for i in range(steps):
         stats = ctx.run_batch(sets[warmup + i], lams, adjs)
+    ev1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    # the same images, one plain call each
-    plain = [s.clone() for s in srcs]
-    torch.cuda.synchronize()
-    p0 = time.perf_counter()
+    gpu_ms = ev0.elapsed_time(ev1)
+    # the same images, one plain call each (a first pass warms the shapes
+    # the plain path picks for each size)
+    plain_s = None
+    plain_exact = None
     if plain_leg:
-        for t, lam, adj in zip(plain, lams, adjs):
+        warm = [s.clone() for s in srcs]
+        for t, lam, adj in zip(warm, lams, adjs):
             ctx.run(t, lam, adj)
-    torch.cuda.synchronize()
-    p1 = time.perf_counter()
+        del warm
+        plain = [s.clone() for s in srcs]
+        torch.cuda.synchronize()
+        p0 = time.perf_counter()
+        pstats = [ctx.run(t, lam, adj) for t, lam, adj in zip(plain, lams, adjs)]
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - p0
     ctx.close()
+    # every image of the last timed batch (and of the plain calls) against
+    # the oracle's digests, passes and lowerings
+    exact = True
+    exams = 0
+    for i, g in enumerate(golden):
+        if not same_input[i]:
+            exact = None if exact is not False else False
+            continue
+        got = sets[warmup + steps - 1][i].cpu().numpy()
+        ok = (_digest(got) == g["output_sha256"] and stats[i].passes == g["passes"]
+              and stats[i].lowerings == g["lowerings"])
+        exact = (exact if exact is not None else True) and ok
+        exams += stats[i].examinations
+    if plain_leg:
+        plain_exact = all(_digest(plain[i].cpu().numpy()) == g["output_sha256"]
+                          and (pstats[i].passes, pstats[i].lowerings) == (g["passes"], g["lowerings"])
+                          for i, g in enumerate(golden) if same_input[i])
+        del plain
+    del sets
+    # Kernel durations: the same batch again with HIP events around every
+    # round launch on the library's stream (a separate pass: the events
+    # cost about 2.5 us a launch).
     prof_kw = dict(ctx_kw)
     if tuned is not None:  # the tuned shape, forced
         prof_kw.update(tile=tuned["tile"][0], steps_per_round=tuned["steps_per_round"],
                        threads=tuned["threads"], variant=tuned["variant"])
     launches, kernel_ms = _kernel_pass(prof_kw, [[s.clone() for s in srcs]], (lams, adjs),
                                        lambda c, ts, l, a: c.run_batch(ts, l, a))
-    # bit-exactness on a sample the oracle finishes quickly: the 12 smallest
-    # images and every 16th image of at most 0.3 Mpixel
-    order = sorted(range(n_images), key=lambda i: Fs[i].size)
-    small = [i for i in range(n_images) if Fs[i].size <= 300_000]
-    sample = sorted(set(order[:12]) | set(small[::16]))
-    exact = True
-    sample_exams = sample_passes = 0
-    for i in sample:
-        ref = oracle.sweep_dirty(Fs[i], lams[i], adjs[i])
-        sample_exams += int(ref.examinations)
-        sample_passes += Fs[i].size * int(ref.passes)
-        got = sets[warmup + steps - 1][i].cpu().numpy()
-        exact &= bool(np.array_equal(got, ref.image))
-        exact &= (stats[i].passes, stats[i].lowerings) == (ref.passes, ref.lowerings)
-        if plain_leg:
-            exact &= bool(np.array_equal(plain[i].cpu().numpy(), ref.image))
     elapsed = t1 - t0
     alg_one = sum(2 * F.size * st.passes for F, st in zip(Fs, stats))
-    kernel_s = kernel_ms / 1e3
-    achieved = alg_one / kernel_s / 1e9 if kernel_s > 0 else None
+    x_method = sum(g["examinations"] for g in golden)
+    px_passes = sum(F.size * st.passes for F, st in zip(Fs, stats))
+    avg_launch_s = kernel_ms / 1e3 / max(launches, 1)
+    achieved = alg_one / max(launches, 1) / avg_launch_s / 1e9 if kernel_ms > 0 else None
+    traffic = _traffic_for("k_round", "batch_512")
     out = {
         "metric": METRIC,
         "value": round(total_px * steps / elapsed / 1e6, 3),
@@ -330,6 +433,7 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512, tune=True
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8", "data": "synthetic",
         "config": {"workload": "batch_512", "images_per_step": n_images,
+                   "pixels_per_step": total_px,
                    "sides": "log-uniform 64..2048", "lambda": "{0,5,20,50}",
                    "adjacency": "8,4", "path": "batched (thin_run_batch)",
                    "graph": graph,
@@ -339,33 +443,35 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, n_images=512, tune=True
                        "candidates": tuned["candidates"], "tuned_ms": round(tuned["ms"], 3),
                        "untuned_ms": round(tuned["default_ms"], 3)}},
         "images_per_s": round(n_images * steps / elapsed, 2),
-        "plain_images_per_s": round(n_images / (p1 - p0), 2) if plain_leg else None,
-        "plain_mpixel_per_s": round(total_px / (p1 - p0) / 1e6, 3) if plain_leg else None,
+        "gpu_ms_per_step": round(gpu_ms / steps, 3),
+        "plain_images_per_s": round(n_images / plain_s, 2) if plain_leg else None,
+        "plain_mpixel_per_s": round(total_px / plain_s / 1e6, 3) if plain_leg else None,
+        "batched_over_plain": round(plain_s / (elapsed / steps), 3) if plain_leg else None,
+        "bit_exact": exact,
+        "bit_exact_plain": plain_exact,
+        "bit_exact_images": sum(same_input),
         "streaming_equiv_frac_of_hbm": round(alg_one * steps / elapsed / 1e9 / HBM_PEAK_GBS, 4),
-        "bit_exact_sample": exact,
         "roofline": {
             "bound": "hbm", "kernel": "k_round",
             "achieved": round(achieved, 2) if achieved else None,
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-            "traffic": _traffic_for("k_round", "batch_512"),
+            "traffic": traffic,
             "launches_per_step": launches,
-            "avg_launch_us": round(kernel_ms * 1e3 / max(launches, 1), 3),
+            "avg_launch_us": round(avg_launch_s * 1e6, 3),
             "alg_bytes_per_launch": round(alg_one / max(launches, 1), 1),
-            "timing": "kernel durations from HIP events in a second pass over the same batch",
+            "timing": "HIP events around every round launch on the library's stream, in a "
+                      "second pass over the same batch",
         },
-        # the method's own work on the oracle-checked sample (dirty-pixel sweep)
-        "method_work": {"images": len(sample), "examinations": sample_exams,
-                        "pixel_passes": sample_passes,
-                        "fraction": round(sample_exams / max(sample_passes, 1), 4)},
+        # the method's own work (oracle dirty-pixel sweep, stored per image)
+        # against the streaming H*W*P pixel-passes and the kernels' own count
+        "method_work": {"examinations": x_method, "pixel_passes": px_passes,
+                        "fraction": round(x_method / max(px_passes, 1), 4),
+                        "gpu_examinations": exams,
+                        "gpu_over_method": round(exams / max(x_method, 1), 3)},
     }
-    if cpu_s > 0:
-        smalls = [(Fs[i], lams[i], adjs[i]) for i in order[: n_images // 2]]
-        v, n, dt = cpu_baseline(smalls, cpu_s)
-        out["cpu_baseline"] = {"value": round(v, 4), "unit": "Mpixel/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"ORACLE-SWEEP-DIRTY, single-thread C, {n} of the "
-                                         f"batch's images (smallest first) in {dt:.1f} s"}
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     return out
 
 
@@ -482,7 +588,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ridges_512",
+    ap.add_argument("--workload", default="batch_512",
                     choices=["ridges_512", "blobs_128", "blobs_8192_u16", "skeleton_512",
                              "gradient_skeleton_512", "batch_512", "serving",
                              "copy_calibration"])

@@ -128,6 +128,10 @@ typedef struct thin_stats {
     uint64_t tile_rounds;  /* tile residencies processed (work done; depends on the engine) */
     uint32_t converged;    /* 1 when stable, 0 when stopped by max_passes */
     uint32_t reserved;
+    uint64_t examinations; /* candidates the kernels characterised (work done; depends on the
+                              engine: tile halos are characterised by every tile that holds
+                              them, and the pixel work-list engine characterises exactly the
+                              candidates whose 3x3 changed since their last characterisation) */
 } thin_stats;
 
 typedef struct thin_image {

@@ -143,6 +143,20 @@ def quantize(mag32, gain, out_dtype=np.uint8):
     return np.minimum(q, np.float32(top)).astype(out_dtype)
 
 
+def quantize_reference(mag64, gain, out_dtype=np.uint8):
+    """D5 in float64: (q, margin) with q = min(top, rint(magnitude * gain))
+    and margin the distance of magnitude * gain from the nearest rounding
+    boundary (a half-integer at or below top + 1/2; infinity where the value
+    is clamped to top).  A stored value computed in lower precision may differ
+    from q only where its error exceeds the margin."""
+    top = np.iinfo(out_dtype).max
+    v = np.asarray(mag64, np.float64) * float(gain)
+    q = np.minimum(np.rint(v), float(top)).astype(out_dtype)
+    margin = np.abs(v - np.floor(v) - 0.5)
+    margin = np.where(v > top + 0.5, np.inf, margin)
+    return q, margin
+
+
 def gradient_image(F, alpha, gain, out_dtype=np.uint8):
     """The stored gradient image (float32 arithmetic, D5)."""
     _, _, mag = gradient(F, alpha, np.float32)

@@ -33,6 +33,7 @@ struct ImgCnt {
     unsigned long long tile_rounds;
     int32_t last_step;   // image-local index of the last step that lowered, -1 if none
     int32_t pad;
+    unsigned long long examinations;  // candidates characterised (section 2.1 tests run)
 };
 
 // Tiles a round launch visits.  With list == nullptr every tile is visited.

@@ -179,6 +179,7 @@ __global__ void k_init_state(ImgCnt* cnt, int nimg, int32_t* tile_last, int ntil
         cnt[i].tile_rounds = 0ull;
         cnt[i].last_step = -1;
         cnt[i].pad = -1;
+        cnt[i].examinations = 0ull;
     }
     if (tile_last && i < 2 * ntiles) tile_last[i] = -1;
 }
@@ -202,7 +203,8 @@ __global__ __launch_bounds__(kThreads) void k_step(const ImgDev* __restrict__ im
     const int i = 2 * (int)blockIdx.y + si;
     const int j = 2 * (int)(blockIdx.x * kThreads + threadIdx.x) + sj;
     bool lowered = false;
-    if (i >= 1 && i <= d.h - 2 && j >= 1 && j <= d.w - 2) {
+    const bool inside = i >= 1 && i <= d.h - 2 && j >= 1 && j <= d.w - 2;
+    if (inside) {
         T* px = static_cast<T*>(d.buf[0]) + (int64_t)i * d.pitch + j;
         const int64_t P = d.pitch;
         const uint32_t v = px[0];
@@ -215,6 +217,9 @@ __global__ __launch_bounds__(kThreads) void k_step(const ImgDev* __restrict__ im
         }
     }
     const unsigned long long ballot = __ballot(lowered);
+    const unsigned long long seen = __ballot(inside);
+    if ((threadIdx.x & 63) == 0 && seen != 0ull)
+        atomicAdd(&cnt->examinations, (unsigned long long)__popcll(seen));
     if ((threadIdx.x & 63) == 0 && ballot != 0ull) {
         atomicAdd(&cnt->lowerings, (unsigned long long)__popcll(ballot));
         atomicMax(&cnt->last_step, step);
@@ -628,14 +633,15 @@ struct Tile {
     static __device__ __forceinline__ int run(const View d, int gy0, int gx0, int t0, int nsteps,
                               const void* src, void* dst, uint16_t* s_img, uint8_t* s_dirty,
                               uint32_t* s_bits, uint32_t* s_cw, const Seed* sd,
-                              const TopoEntry* lut, int* s_count, int* s_last, int tid,
-                              int& last_tau)
+                              const TopoEntry* lut, int* s_count, int* s_last, int* s_exam,
+                              int tid, int& last_tau)
     {
         const int ry0 = gy0 - K, rx0 = gx0 - K;
         const bool seeded = SEED && sd != nullptr && sd->r > 0;
         if (tid == 0) {
             *s_count = 0;
             *s_last = -1;
+            *s_exam = 0;
         }
         if constexpr (SEED)
             for (int i = tid; i < TH * WPR; i += NT) s_bits[i] = 0u;
@@ -684,6 +690,7 @@ struct Tile {
 
         const uint32_t lambda = d.lambda;
         int my_count = 0, my_last = -1;  // interior lowerings, last step with one
+        int my_exams = 0;                // candidates characterised
         // Each thread owns fixed positions of the candidate lattice (one in
         // four pixels, rows and columns of the step's parity): the region's
         // origin is even (tile side and halo are even), so the candidate of
@@ -707,6 +714,7 @@ struct Tile {
                 {
                     if (!s_dirty[o]) continue;
                     s_dirty[o] = 0;
+                    ++my_exams;
                     uint16_t* p = s_img + o;
                     const uint32_t v = p[0];
                     const uint32_t nbv[8] = {p[1], p[-RWP + 1], p[-RWP], p[-RWP - 1],
@@ -740,6 +748,7 @@ struct Tile {
             atomicAdd(s_count, my_count);
             atomicMax(s_last, my_last);
         }
+        if (my_exams) atomicAdd(s_exam, my_exams);
         __syncthreads();
         if constexpr (SEED) {
             if (sd != nullptr) {
@@ -829,7 +838,7 @@ struct RTile {
     static __device__ __forceinline__ void step(Cells& q, uint16_t* s_img, int tau, int r_lo,
                                                 int r_hi, int c_lo, int c_hi,
                                                 const TopoEntry* lut, uint32_t lambda,
-                                                int& my_count, bool& inner)
+                                                int& my_count, int& my_exams, bool& inner)
     {
         constexpr int si = C >> 1, sj = C & 1;
         constexpr int P = (C + 3) & 3, pi = P >> 1, pj = P & 1;
@@ -860,6 +869,7 @@ struct RTile {
             if (lr < r_lo || lr > r_hi || lc < c_lo || lc > c_hi) continue;
             if (((q.pend[k] >> C) & 1u) == 0u) continue;
             q.pend[k] &= ~(1u << C);
+            ++my_exams;
             uint32_t(&w)[16] = q.win[k];
             const uint32_t nb[8] = {w[4 * ci + cj + 1],       w[4 * (ci - 1) + cj + 1],
                                     w[4 * (ci - 1) + cj],     w[4 * (ci - 1) + cj - 1],
@@ -882,13 +892,13 @@ struct RTile {
     static __device__ __forceinline__ void full_step(Cells& q, const View& d, int ry0, int rx0,
                                                      uint16_t* s_img, int tau,
                                                      const TopoEntry* lut, int& my_last,
-                                                     int& my_count)
+                                                     int& my_count, int& my_exams)
     {
         // Exact region after tau steps, clipped to the image interior.
         const int r_lo = max(tau + 1, 1 - ry0), r_hi = min(RH - 2 - tau, d.h - 2 - ry0);
         const int c_lo = max(tau + 1, 1 - rx0), c_hi = min(RW - 2 - tau, d.w - 2 - rx0);
         bool inner = false;
-        step<C>(q, s_img, tau, r_lo, r_hi, c_lo, c_hi, lut, d.lambda, my_count, inner);
+        step<C>(q, s_img, tau, r_lo, r_hi, c_lo, c_hi, lut, d.lambda, my_count, my_exams, inner);
         if (inner) my_last = tau;
         __syncthreads();
     }
@@ -897,13 +907,14 @@ struct RTile {
     static __device__ __forceinline__ int run(const View d, int gy0, int gx0, int t0, int nsteps,
                               const void* src, void* dst, uint16_t* s_img, uint8_t*, uint32_t*,
                               uint32_t*, const Seed*, const TopoEntry* lut, int* s_count,
-                              int* s_last, int tid, int& last_tau)
+                              int* s_last, int* s_exam, int tid, int& last_tau)
     {
         (void)t0;  // a multiple of 4: step tau has class tau mod 4
         const int ry0 = gy0 - K, rx0 = gx0 - K;
         if (tid == 0) {
             *s_count = 0;
             *s_last = -1;
+            *s_exam = 0;
         }
         // The barrier after the windows are read also orders the counter
         // reset above before the steps' updates.
@@ -930,11 +941,15 @@ struct RTile {
         __syncthreads();
 
         int my_count = 0, my_last = -1;  // interior lowerings, last step with one
+        int my_exams = 0;                // candidates characterised
         for (int tau = 0; tau < nsteps; tau += 4) {
-            full_step<0>(q, d, ry0, rx0, s_img, tau, lut, my_last, my_count);
-            if (tau + 1 < nsteps) full_step<1>(q, d, ry0, rx0, s_img, tau + 1, lut, my_last, my_count);
-            if (tau + 2 < nsteps) full_step<2>(q, d, ry0, rx0, s_img, tau + 2, lut, my_last, my_count);
-            if (tau + 3 < nsteps) full_step<3>(q, d, ry0, rx0, s_img, tau + 3, lut, my_last, my_count);
+            full_step<0>(q, d, ry0, rx0, s_img, tau, lut, my_last, my_count, my_exams);
+            if (tau + 1 < nsteps)
+                full_step<1>(q, d, ry0, rx0, s_img, tau + 1, lut, my_last, my_count, my_exams);
+            if (tau + 2 < nsteps)
+                full_step<2>(q, d, ry0, rx0, s_img, tau + 2, lut, my_last, my_count, my_exams);
+            if (tau + 3 < nsteps)
+                full_step<3>(q, d, ry0, rx0, s_img, tau + 3, lut, my_last, my_count, my_exams);
         }
 
         store(d, gy0, gx0, src, dst, s_img, tid);
@@ -942,6 +957,7 @@ struct RTile {
             atomicAdd(s_count, my_count);
             atomicMax(s_last, my_last);
         }
+        if (my_exams) atomicAdd(s_exam, my_exams);
         __syncthreads();
         last_tau = *s_last;
         return *s_count;
@@ -1051,7 +1067,7 @@ struct BTile {
                                               const void* src, void* dst, E* s_img,
                                               uint8_t* s_flags, uint32_t* s_bits, uint32_t* s_cw,
                                               const Seed* sd, const TopoEntry* lut, int* s_count,
-                                              int* s_last, int tid, int& last_tau)
+                                              int* s_last, int* s_exam, int tid, int& last_tau)
     {
         (void)t0;  // a multiple of 4: step tau has class tau mod 4
         uint32_t* s_db = reinterpret_cast<uint32_t*>(s_flags);           // [4][LAT_H][LWW]
@@ -1063,6 +1079,7 @@ struct BTile {
         if (tid == 0) {
             *s_count = 0;
             *s_last = -1;
+            *s_exam = 0;
         }
         if constexpr (SEED)
             for (int i = tid; i < TH * WPR; i += NT) s_bits[i] = 0u;
@@ -1123,6 +1140,7 @@ struct BTile {
         const int myw = lane < WAVE_WORDS ? wave * WAVE_WORDS + lane : CLASS_WORDS;  // its word
         const int wa = myw / LWW, wj = myw - (myw / LWW) * LWW;
         int my_count = 0, my_last = -1;  // interior lowerings, last step with one
+        int my_exams = 0;                // candidates characterised (thread 0 counts the lists)
         for (int tau = 0; tau < nsteps; ++tau) {
             const int c = tau & 3, si = c >> 1, sj = c & 1;
             // Exact region after tau steps, clipped to the image interior,
@@ -1190,7 +1208,10 @@ struct BTile {
             }
             __syncthreads();
             const int total = s_total[tau & 1];
-            if (tid == 0) s_total[(tau + 1) & 1] = 0;
+            if (tid == 0) {
+                s_total[(tau + 1) & 1] = 0;
+                my_exams += total;
+            }
             bool inner = false;
             for (int i = tid; i < total; i += NT) {
                 const int cell = s_list[i];
@@ -1225,6 +1246,7 @@ struct BTile {
             atomicAdd(s_count, my_count);
             atomicMax(s_last, my_last);
         }
+        if (my_exams) atomicAdd(s_exam, my_exams);
         __syncthreads();
         if constexpr (SEED) {
             if (sd != nullptr) {
@@ -1268,7 +1290,7 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
                           typename TileOf<TH, TW, K, NT, VAR, E>::Elem* s_img, uint8_t* s_dirty,
                           uint32_t* s_bits, uint32_t* s_cw, const TopoEntry* __restrict__ lut_g,
                           TopoEntry* s_lut, int& lut_adj, int* s_count, int* s_last,
-                          const WorkList& wl, int kflags)
+                          int* s_exam, const WorkList& wl, int kflags)
 {
     using T = TileOf<TH, TW, K, NT, VAR, E>;
     const int tid = threadIdx.x;
@@ -1338,10 +1360,11 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
     sd.g = g;
     int last_tau;
     const int count = T::run(v, gy0, gx0, t0, nsteps, src, dst, s_img, s_dirty, s_bits, s_cw,
-                             var_seeded(VAR) ? &sd : nullptr, s_lut, s_count, s_last, tid,
-                             last_tau);
+                             var_seeded(VAR) ? &sd : nullptr, s_lut, s_count, s_last, s_exam,
+                             tid, last_tau);
     if (tid == 0) {
         atomicAdd(&cnt[slot].tile_rounds, 1ull);
+        atomicAdd(&cnt[slot].examinations, (unsigned long long)*s_exam);
         if (last_tau >= 0) {
             __hip_atomic_store(&st[1], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             atomicAdd(&cnt[slot].lowerings, (unsigned long long)count);
@@ -1384,7 +1407,7 @@ __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, I
     __shared__ uint32_t s_bits[T::BITS_WORDS];
     __shared__ uint32_t s_cw[T::CW_WORDS];
     __shared__ TopoEntry s_lut[256];
-    __shared__ int s_count, s_last;
+    __shared__ int s_count, s_last, s_exam;
     int lut_adj = -1;
     const bool all = wl.list == nullptr || round == wl.full;
     const int n = all ? ntiles : wl.count[round % 3];
@@ -1393,8 +1416,8 @@ __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, I
     for (int i = blockIdx.x; i < n; i += gridDim.x)
         round_tile<TH, TW, K, NT, VAR, E>(imgs, cnt, tile_img, tile_last, all ? i : mine[i], round,
                                           ntiles, hist_bits, hist_round, s_img, s_dirty, s_bits,
-                                          s_cw, lut_g, s_lut, lut_adj, &s_count, &s_last, wl,
-                                          kflags);
+                                          s_cw, lut_g, s_lut, lut_adj, &s_count, &s_last, &s_exam,
+                                          wl, kflags);
 }
 
 // ------------------------------------------------------------------ k_coop
@@ -1422,7 +1445,7 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
     __shared__ uint32_t s_bits[T::BITS_WORDS];
     __shared__ uint32_t s_cw[T::CW_WORDS];
     __shared__ TopoEntry s_lut[256];
-    __shared__ int s_count, s_last;
+    __shared__ int s_count, s_last, s_exam;
     const int tid = threadIdx.x;
     int lut_adj = -1;
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
@@ -1436,7 +1459,7 @@ __global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, Im
             mine += round_tile<TH, TW, K, NT, VAR, E>(imgs, cnt, tile_img, tile_last, g, round,
                                                  ntiles, hist_bits, hist_round, s_img, s_dirty,
                                                  s_bits, s_cw, lut_g, s_lut, lut_adj, &s_count,
-                                                 &s_last, WorkList{}, kflags);
+                                                 &s_last, &s_exam, WorkList{}, kflags);
         if (tid == 0 && mine) atomicAdd(&active[round % 3], mine);
         // Stores of every wave must be acknowledged before the grid barrier
         // publishes them.

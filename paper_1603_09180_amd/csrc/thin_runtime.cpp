@@ -106,6 +106,7 @@ struct Retired {
 };
 
 constexpr int kServeSlots = 1 << 14;          // resident images at most
+constexpr int kMaxChunk = 4;                  // rounds launched between counter read-backs
 constexpr uint64_t kServeDefaultBudget = 1ull << 30;
 
 }  // namespace
@@ -154,6 +155,8 @@ struct thin_ctx {
 
     // autotuned shapes by size class (log2 total pixels, log2 pixels per image)
     std::map<std::pair<int, int>, TileShape> tuned;
+
+    int last_launches = 0;         // round launches of the last tiled run
 
     std::string last_error;
 };
@@ -357,6 +360,7 @@ void fill_stats(thin_stats* st, const ImgCnt& c, int steps_done, int max_steps, 
     }
     st->lowerings = c.lowerings;
     st->tile_rounds = c.tile_rounds;
+    st->examinations = c.examinations;
     const bool stable = c.last_step < steps_done - 4;
     if (stable) {
         st->converged = 1;
@@ -411,6 +415,198 @@ int chunk_graph(thin_ctx* ctx, const std::vector<uint64_t>& key, F record, hipGr
     return THIN_OK;
 }
 
+// Device memory one tiled run works in (context-owned buffers, or carved out
+// of the library's static scratch array by the no-allocation entry point).
+struct TiledBufs {
+    ImgDev* imgs;
+    ImgCnt* cnt;
+    int32_t* tile_img;    // tile -> image (unused with one image)
+    int32_t* tile_last;   // 2 per tile
+    uint32_t* hist_bits;  // 2 * ntiles * history_words(shape)
+    int32_t* hist_round;  // 2 per tile
+    int32_t* wl_list;     // 2 per tile
+    int32_t* wl_meta;     // 4 + 1 per tile
+    int32_t* small;       // 16 words
+};
+
+// Launches the rounds of a tiled run whose descriptors (host copy h_imgs,
+// device copy b.imgs) and tile map are in place, until every image is stable
+// or at its step cap, brings every image's state home into its own buffer
+// and fills the statistics (stats[src_index[i]] for image i; src_index may
+// be null for the identity).  allocate: graphs and profiling events may be
+// created (the no-allocation entry point passes false).
+int drive_tiled(thin_ctx* ctx, TileShape shape, const ImgDev* h_imgs, int nimg, int ntiles,
+                const TiledBufs& b, const int* src_index, thin_stats* stats, bool allocate)
+{
+    const int K = shape.k;
+    int max_steps_all = 0;
+    for (int i = 0; i < nimg; ++i) max_steps_all = std::max(max_steps_all, h_imgs[i].max_steps);
+    // (Only worth a longer dependency chain per visit when blocks visit
+    // several tiles each.)
+    const int grid = ctx->num_cus * thin::round_blocks_per_cu(shape);
+    thin::WorkList wl{};
+    wl.full = 0;
+    if (ntiles > 2 * grid) wl.list = b.wl_list;
+    wl.count = b.wl_meta;
+    wl.listed = wl.count + 4;
+    wl.cap = ntiles;
+    HIP_TRY(ctx, thin::launch_init_state(ctx->stream, b.cnt, nimg, b.tile_last, ntiles,
+                                         b.hist_round, wl));
+
+    const int rounds_cap =
+        (max_steps_all == INT_MAX) ? INT_MAX : (max_steps_all + K - 1) / K;
+    size_t ev_used = 0;        // profiling events recorded by this call
+    int launched = 0;          // rounds enqueued so far
+    int chunk = 2;
+    int pending = -1;          // snapshot slot in flight (-1 none)
+    int pending_rounds = 0;
+    bool done = false;
+    auto all_done = [&](const ImgCnt* snap, int rounds) {
+        for (int i = 0; i < nimg; ++i) {
+            const int steps = (int)std::min<int64_t>((int64_t)rounds * K, h_imgs[i].max_steps);
+            const bool stable = snap[i].last_step < steps - 4;
+            if (!stable && steps < h_imgs[i].max_steps) return false;
+        }
+        return true;
+    };
+    const int kflags = thin::kStateIsTile | (nimg == 1 ? thin::kOneImage : 0);
+    int dtypes = 0;
+    for (int i = 0; i < nimg; ++i) dtypes |= h_imgs[i].dtype == THIN_U8 ? 1 : 2;
+    const bool profile = ctx->profile && allocate;
+    // Graph mode: a chunk of rounds is one graph replay; the launches read
+    // their round from a device counter that the graph's last node advances.
+    const bool use_graph = ctx->graph && !profile && allocate;
+    int32_t* d_round = b.small + 8;
+    if (use_graph) HIP_TRY(ctx, hipMemsetAsync(d_round, 0, sizeof(int32_t), ctx->stream));
+    auto record_rounds = [&](hipStream_t st, int count) -> hipError_t {
+        for (int k = 0; k < count; ++k) {
+            const hipError_t e = launch_rounds_split(st, shape, b.imgs, b.cnt, b.tile_img,
+                                                     b.tile_last, ntiles, k, ctx->d_lut,
+                                                     ctx->num_cus, b.hist_bits, b.hist_round, wl,
+                                                     d_round, kflags, dtypes);
+            if (e != hipSuccess) return e;
+        }
+        return thin::launch_advance(st, d_round, count);
+    };
+    int rc;
+    while (!done) {
+        const int n = std::min(chunk, rounds_cap - launched);
+        if (use_graph) {
+            hipGraphExec_t ge = nullptr;
+            if (n == chunk) {
+                const std::vector<uint64_t> key = {
+                    (uint64_t)shape.th, (uint64_t)shape.tw, (uint64_t)shape.k, (uint64_t)shape.nt,
+                    (uint64_t)shape.var, (uint64_t)ntiles, (uint64_t)grid, (uint64_t)n,
+                    (uint64_t)(uintptr_t)b.imgs, (uint64_t)(uintptr_t)b.cnt,
+                    (uint64_t)(uintptr_t)b.tile_img, (uint64_t)(uintptr_t)b.tile_last,
+                    (uint64_t)(uintptr_t)b.hist_bits, (uint64_t)(uintptr_t)b.hist_round,
+                    (uint64_t)(uintptr_t)wl.list, (uint64_t)(uintptr_t)wl.count,
+                    (uint64_t)(uintptr_t)ctx->d_lut, (uint64_t)(uintptr_t)d_round,
+                    // what the recorded launches bake in besides pointers and sizes:
+                    // the one-image shortcut and which pixel-type launches exist
+                    (uint64_t)kflags, (uint64_t)dtypes};
+                if ((rc = chunk_graph(ctx, key, [&](hipStream_t st) { return record_rounds(st, n); },
+                                      &ge)))
+                    return rc;
+                HIP_TRY(ctx, hipGraphLaunch(ge, ctx->stream));
+            } else {
+                HIP_TRY(ctx, record_rounds(ctx->stream, n));
+            }
+            launched += n;
+        } else {
+            for (int k = 0; k < n; ++k) {
+                if (profile) {
+                    if ((rc = timed_round(ctx, ev_used, shape, b.imgs, b.cnt, b.tile_img,
+                                          b.tile_last, ntiles, launched, grid, b.hist_bits,
+                                          b.hist_round, wl, kflags, dtypes)))
+                        return rc;
+                } else {
+                    HIP_TRY(ctx, launch_rounds_split(ctx->stream, shape, b.imgs, b.cnt,
+                                                     b.tile_img, b.tile_last, ntiles, launched,
+                                                     ctx->d_lut, ctx->num_cus, b.hist_bits,
+                                                     b.hist_round, wl, nullptr, kflags, dtypes));
+                }
+                ++launched;
+            }
+        }
+        // Counters are read back one chunk behind (the host never waits for
+        // the chunk it just launched), so a run stops at most one chunk past
+        // stability; chunks stay short for that reason.
+        const int slot = (pending < 0) ? 0 : 1 - pending;
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_snap[slot], b.cnt, sizeof(ImgCnt) * nimg,
+                                    hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(ctx, hipEventRecord(ctx->ev[slot], ctx->stream));
+        if (launched >= rounds_cap) break;
+        if (pending >= 0) {
+            HIP_TRY(ctx, hipEventSynchronize(ctx->ev[pending]));
+            if (all_done(ctx->h_snap[pending], pending_rounds)) done = true;
+        }
+        pending = slot;
+        pending_rounds = launched;
+        chunk = std::min(chunk * 2, kMaxChunk);
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_snap[0], b.cnt, sizeof(ImgCnt) * nimg,
+                                hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const ImgCnt* fin = ctx->h_snap[0];
+    if (profile) {
+        if ((rc = collect_profile(ctx, ev_used))) return rc;
+        for (int i = 0; i < nimg; ++i) ctx->prof_tile_rounds += fin[i].tile_rounds;
+    }
+
+    // Bring results home: after r rounds an image's state is in buf[r & 1],
+    // where r stops growing once its step cap is reached.
+    for (int i = 0; i < nimg; ++i) {
+        const ImgDev& d = h_imgs[i];
+        const int r_img = std::min(launched, (d.max_steps == INT_MAX) ? INT_MAX
+                                                                       : (d.max_steps + K - 1) / K);
+        if (r_img & 1) {
+            const size_t bpp = d.dtype == THIN_U8 ? 1 : 2;
+            HIP_TRY(ctx, hipMemcpy2DAsync(d.buf[0], d.pitch * bpp, d.buf[1], d.pitch * bpp,
+                                          (size_t)d.w * bpp, (size_t)d.h,
+                                          hipMemcpyDeviceToDevice, ctx->stream));
+        }
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->last_launches = launched;
+
+    bool limited = false;
+    for (int i = 0; i < nimg; ++i) {
+        const ImgDev& d = h_imgs[i];
+        const int steps = (int)std::min<int64_t>((int64_t)launched * K, d.max_steps);
+        thin_stats st;
+        fill_stats(&st, fin[i], steps, d.max_steps, false);
+        if (!st.converged) limited = true;
+        if (stats) stats[src_index ? src_index[i] : i] = st;
+    }
+    return limited ? fail(ctx, THIN_ELIMIT, "max_passes reached before stability") : THIN_OK;
+}
+
+// Descriptor of image `im` for a tiled run with `shape`, its twin at `twin`,
+// its tiles from tile0 on, counter slot `slot`.
+ImgDev describe_tiled(const thin_image& im, TileShape shape, void* twin, int32_t tile0,
+                      int32_t slot, int max_steps)
+{
+    ImgDev d{};
+    d.buf[0] = im.image;
+    d.buf[1] = twin;
+    d.pitch = pitch_of(im);
+    d.h = (int32_t)im.h;
+    d.w = (int32_t)im.w;
+    d.dtype = im.dtype;
+    d.lambda = im.lambda;
+    d.adj = table_index(im);
+    d.tiles_y = (int32_t)((im.h + shape.th - 1) / shape.th);
+    d.tiles_x = (int32_t)((im.w + shape.tw - 1) / shape.tw);
+    d.tile0 = tile0;
+    d.round0 = 0;
+    d.max_steps = max_steps;
+    d.slot = slot;
+    d.state0 = d.tile0;
+    return d;
+}
+
 int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work, thin_stats* stats)
 {
     int64_t total_px = 0;
@@ -418,7 +614,6 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
     const TileShape shape = choose_shape(ctx, total_px, (int64_t)work.size());
     if (!thin::tile_shape_supported(shape))
         return fail(ctx, THIN_EINVAL, "unsupported tile shape %dx%d k=%d", shape.th, shape.tw, shape.k);
-    const int K = shape.k;
     const int max_steps = steps_cap(ctx);
 
     Plan plan;
@@ -434,22 +629,9 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
     if (rc) return rc;
     for (size_t n = 0; n < work.size(); ++n) {
         const thin_image& im = ims[work[n]];
-        ImgDev d{};
-        d.buf[0] = im.image;
-        d.buf[1] = static_cast<char*>(ctx->twin.ptr) + twin_off[n];
-        d.pitch = pitch_of(im);
-        d.h = (int32_t)im.h;
-        d.w = (int32_t)im.w;
-        d.dtype = im.dtype;
-        d.lambda = im.lambda;
-        d.adj = table_index(im);
-        d.tiles_y = (int32_t)((im.h + shape.th - 1) / shape.th);
-        d.tiles_x = (int32_t)((im.w + shape.tw - 1) / shape.tw);
-        d.tile0 = (int32_t)plan.tile_img.size();
-        d.round0 = 0;
-        d.max_steps = max_steps;
-        d.slot = (int32_t)plan.imgs.size();
-        d.state0 = d.tile0;
+        const ImgDev d = describe_tiled(im, shape, static_cast<char*>(ctx->twin.ptr) + twin_off[n],
+                                        (int32_t)plan.tile_img.size(),
+                                        (int32_t)plan.imgs.size(), max_steps);
         const int64_t nt = (int64_t)d.tiles_x * d.tiles_y;
         if ((int64_t)plan.tile_img.size() + nt > INT_MAX / 2)
             return fail(ctx, THIN_EINVAL, "too many tiles in one call");
@@ -468,147 +650,28 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
         return rc;
     if ((rc = ensure(ctx, ctx->hist_round, sizeof(int32_t) * 2 * (size_t)ntiles))) return rc;
     if ((rc = ensure_snap(ctx, nimg))) return rc;
-
-    ImgDev* d_imgs = static_cast<ImgDev*>(ctx->imgs.ptr);
-    ImgCnt* d_cnt = static_cast<ImgCnt*>(ctx->cnt.ptr);
-    int32_t* d_tile_img = static_cast<int32_t*>(ctx->tile_img.ptr);
-    int32_t* d_tile_last = static_cast<int32_t*>(ctx->tile_last.ptr);
-    uint32_t* d_hist_bits = static_cast<uint32_t*>(ctx->hist_bits.ptr);
-    int32_t* d_hist_round = static_cast<int32_t*>(ctx->hist_round.ptr);
-    HIP_TRY(ctx, hipMemcpyAsync(d_imgs, plan.imgs.data(), sizeof(ImgDev) * nimg,
-                                hipMemcpyHostToDevice, ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(d_tile_img, plan.tile_img.data(), sizeof(int32_t) * ntiles,
-                                hipMemcpyHostToDevice, ctx->stream));
     if ((rc = ensure(ctx, ctx->small, 64))) return rc;
     // Work lists: round 0 visits every tile, later rounds the tiles queued
     // by the round before.
     if ((rc = ensure(ctx, ctx->wl_list, sizeof(int32_t) * 2 * (size_t)ntiles))) return rc;
     if ((rc = ensure(ctx, ctx->wl_meta, sizeof(int32_t) * (4 + (size_t)ntiles)))) return rc;
-    // (Only worth a longer dependency chain per visit when blocks visit
-    // several tiles each.)
-    const int grid = ctx->num_cus * thin::round_blocks_per_cu(shape);
-    thin::WorkList wl{};
-    wl.full = 0;
-    if (ntiles > 2 * grid) wl.list = static_cast<int32_t*>(ctx->wl_list.ptr);
-    wl.count = static_cast<int32_t*>(ctx->wl_meta.ptr);
-    wl.listed = wl.count + 4;
-    wl.cap = ntiles;
-    HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, nimg, d_tile_last, ntiles,
-                                         d_hist_round, wl));
 
-    const int rounds_cap = (max_steps == INT_MAX) ? INT_MAX : (max_steps + K - 1) / K;
-    size_t ev_used = 0;        // profiling events recorded by this call
-    int launched = 0;          // rounds enqueued so far
-    int checked_upto = -1;     // rounds covered by the last evaluated snapshot
-    int chunk = 2;
-    int pending = -1;          // snapshot slot in flight (-1 none)
-    int pending_rounds = 0;
-    bool done = false;
-    auto all_done = [&](const ImgCnt* snap, int rounds) {
-        for (int i = 0; i < nimg; ++i) {
-            const int steps = (int)std::min<int64_t>((int64_t)rounds * K, plan.imgs[i].max_steps);
-            const bool stable = snap[i].last_step < steps - 4;
-            if (!stable && steps < plan.imgs[i].max_steps) return false;
-        }
-        return true;
-    };
-    const int kflags = thin::kStateIsTile | (nimg == 1 ? thin::kOneImage : 0);
-    int dtypes = 0;
-    for (const ImgDev& d : plan.imgs) dtypes |= d.dtype == THIN_U8 ? 1 : 2;
-    // Graph mode: a chunk of rounds is one graph replay; the launches read
-    // their round from a device counter that the graph's last node advances.
-    const bool use_graph = ctx->graph && !ctx->profile;
-    int32_t* d_round = static_cast<int32_t*>(ctx->small.ptr) + 8;
-    if (use_graph) HIP_TRY(ctx, hipMemsetAsync(d_round, 0, sizeof(int32_t), ctx->stream));
-    auto record_rounds = [&](hipStream_t st, int count) -> hipError_t {
-        for (int k = 0; k < count; ++k) {
-            const hipError_t e = launch_rounds_split(st, shape, d_imgs, d_cnt, d_tile_img,
-                                                     d_tile_last, ntiles, k, ctx->d_lut,
-                                                     ctx->num_cus,
-                                                     d_hist_bits, d_hist_round, wl, d_round,
-                                                     kflags, dtypes);
-            if (e != hipSuccess) return e;
-        }
-        return thin::launch_advance(st, d_round, count);
-    };
-    while (!done) {
-        const int n = std::min(chunk, rounds_cap - launched);
-        if (use_graph) {
-            hipGraphExec_t ge = nullptr;
-            if (n == chunk) {
-                const std::vector<uint64_t> key = {
-                    (uint64_t)shape.th, (uint64_t)shape.tw, (uint64_t)shape.k, (uint64_t)shape.nt,
-                    (uint64_t)shape.var, (uint64_t)ntiles, (uint64_t)grid, (uint64_t)n,
-                    (uint64_t)(uintptr_t)d_imgs, (uint64_t)(uintptr_t)d_cnt,
-                    (uint64_t)(uintptr_t)d_tile_img, (uint64_t)(uintptr_t)d_tile_last,
-                    (uint64_t)(uintptr_t)d_hist_bits, (uint64_t)(uintptr_t)d_hist_round,
-                    (uint64_t)(uintptr_t)wl.list, (uint64_t)(uintptr_t)wl.count,
-                    (uint64_t)(uintptr_t)ctx->d_lut, (uint64_t)(uintptr_t)d_round};
-                if ((rc = chunk_graph(ctx, key, [&](hipStream_t st) { return record_rounds(st, n); },
-                                      &ge)))
-                    return rc;
-                HIP_TRY(ctx, hipGraphLaunch(ge, ctx->stream));
-            } else {
-                HIP_TRY(ctx, record_rounds(ctx->stream, n));
-            }
-            launched += n;
-        } else {
-            for (int k = 0; k < n; ++k) {
-                if ((rc = timed_round(ctx, ev_used, shape, d_imgs, d_cnt, d_tile_img, d_tile_last,
-                                      ntiles, launched, grid, d_hist_bits, d_hist_round, wl,
-                                      kflags, dtypes)))
-                    return rc;
-                ++launched;
-            }
-        }
-        const int slot = (pending < 0) ? 0 : 1 - pending;
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_snap[slot], d_cnt, sizeof(ImgCnt) * nimg,
-                                    hipMemcpyDeviceToHost, ctx->stream));
-        HIP_TRY(ctx, hipEventRecord(ctx->ev[slot], ctx->stream));
-        if (launched >= rounds_cap) break;
-        if (pending >= 0) {
-            HIP_TRY(ctx, hipEventSynchronize(ctx->ev[pending]));
-            checked_upto = pending_rounds;
-            if (all_done(ctx->h_snap[pending], pending_rounds)) done = true;
-        }
-        pending = slot;
-        pending_rounds = launched;
-        chunk = std::min(chunk * 2, 16);
-    }
-    (void)checked_upto;
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    HIP_TRY(ctx, hipMemcpy(ctx->h_snap[0], d_cnt, sizeof(ImgCnt) * nimg, hipMemcpyDeviceToHost));
-    const ImgCnt* fin = ctx->h_snap[0];
-    if (ctx->profile) {
-        if ((rc = collect_profile(ctx, ev_used))) return rc;
-        for (int i = 0; i < nimg; ++i) ctx->prof_tile_rounds += fin[i].tile_rounds;
-    }
-
-    // Bring results home: after r rounds an image's state is in buf[r & 1],
-    // where r stops growing once its step cap is reached.
-    for (int i = 0; i < nimg; ++i) {
-        const ImgDev& d = plan.imgs[i];
-        const int r_img = std::min(launched, (d.max_steps == INT_MAX) ? INT_MAX
-                                                                       : (d.max_steps + K - 1) / K);
-        if (r_img & 1) {
-            const size_t bpp = d.dtype == THIN_U8 ? 1 : 2;
-            HIP_TRY(ctx, hipMemcpy2DAsync(d.buf[0], d.pitch * bpp, d.buf[1], d.pitch * bpp,
-                                          (size_t)d.w * bpp, (size_t)d.h,
-                                          hipMemcpyDeviceToDevice, ctx->stream));
-        }
-    }
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-
-    bool limited = false;
-    for (int i = 0; i < nimg; ++i) {
-        const ImgDev& d = plan.imgs[i];
-        const int steps = (int)std::min<int64_t>((int64_t)launched * K, d.max_steps);
-        thin_stats st;
-        fill_stats(&st, fin[i], steps, d.max_steps, false);
-        if (!st.converged) limited = true;
-        if (stats) stats[plan.src_index[i]] = st;
-    }
-    return limited ? fail(ctx, THIN_ELIMIT, "max_passes reached before stability") : THIN_OK;
+    TiledBufs b{};
+    b.imgs = static_cast<ImgDev*>(ctx->imgs.ptr);
+    b.cnt = static_cast<ImgCnt*>(ctx->cnt.ptr);
+    b.tile_img = static_cast<int32_t*>(ctx->tile_img.ptr);
+    b.tile_last = static_cast<int32_t*>(ctx->tile_last.ptr);
+    b.hist_bits = static_cast<uint32_t*>(ctx->hist_bits.ptr);
+    b.hist_round = static_cast<int32_t*>(ctx->hist_round.ptr);
+    b.wl_list = static_cast<int32_t*>(ctx->wl_list.ptr);
+    b.wl_meta = static_cast<int32_t*>(ctx->wl_meta.ptr);
+    b.small = static_cast<int32_t*>(ctx->small.ptr);
+    HIP_TRY(ctx, hipMemcpyAsync(b.imgs, plan.imgs.data(), sizeof(ImgDev) * nimg,
+                                hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(b.tile_img, plan.tile_img.data(), sizeof(int32_t) * ntiles,
+                                hipMemcpyHostToDevice, ctx->stream));
+    return drive_tiled(ctx, shape, plan.imgs.data(), nimg, ntiles, b, plan.src_index.data(), stats,
+                       true);
 }
 
 // ---------------------------------------------------------- cooperative engine
@@ -1305,7 +1368,7 @@ int thin_serve_step(thin_ctx* ctx, int32_t rounds, uint64_t* done_tags, thin_sta
         // New residents: counters and tile state start empty (-1 everywhere).
         for (Resident& r : ctx->resident) {
             if (!r.fresh) continue;
-            ImgCnt c{0ull, 0ull, -1, -1};
+            ImgCnt c{0ull, 0ull, -1, -1, 0ull};
             ctx->serve_snap[r.slot] = c;
             HIP_TRY(ctx, hipMemcpyAsync(d_cnt + r.slot, &ctx->serve_snap[r.slot], sizeof c,
                                         hipMemcpyHostToDevice, ctx->stream));

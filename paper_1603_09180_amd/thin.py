@@ -68,6 +68,7 @@ class thin_stats(ctypes.Structure):
         ("tile_rounds", ctypes.c_uint64),
         ("converged", ctypes.c_uint32),
         ("reserved", ctypes.c_uint32),
+        ("examinations", ctypes.c_uint64),
     ]
 
 
@@ -237,10 +238,12 @@ class Stats:
     lowerings: int
     tile_rounds: int
     converged: bool
+    examinations: int = 0
 
     @staticmethod
     def of(s: thin_stats) -> "Stats":
-        return Stats(int(s.passes), int(s.lowerings), int(s.tile_rounds), bool(s.converged))
+        return Stats(int(s.passes), int(s.lowerings), int(s.tile_rounds), bool(s.converged),
+                     int(s.examinations))
 
 
 def _adj_code(adj) -> int:

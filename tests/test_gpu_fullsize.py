@@ -26,6 +26,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "full_size.json")))
+BATCH = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batch_512.json")))
 
 
 def say(*a):
@@ -65,3 +66,30 @@ def test_full_size(name, make):
     assert np.isin(np.unique(out), np.unique(F)).all()
     assert np.array_equal(out[0], F[0]) and np.array_equal(out[-1], F[-1])
     assert np.array_equal(out[:, 0], F[:, 0]) and np.array_equal(out[:, -1], F[:, -1])
+
+
+def test_batch_512_every_image():
+    """The whole 512-image batch (sides log-uniform 64..2048, lambda from
+    {0, 5, 20, 50}) in one thin_run_batch call, in the benchmark's launch
+    configuration (default context, automatic shape): every image's bytes
+    (by digest), passes and lowerings equal the oracle's stored ones, and the
+    kernels characterised at least as many candidates as the oracle's
+    dirty-pixel sweep needs."""
+    recs = BATCH["images"]
+    jobs = synth.batch_512_uneven(len(recs))
+    Fs = [j.image() for j in jobs]
+    same = [digest(F) == g["input_sha256"] for F, g in zip(Fs, recs)]
+    assert sum(same) >= len(recs) // 2, "the generator does not reproduce the stored inputs here"
+    ts = [torch.from_numpy(F).cuda() for F in Fs]
+    say("case batch_512", len(ts), "images")
+    with thin.Context() as ctx:
+        sts = ctx.run_batch(ts, [j.lam for j in jobs], [j.adj for j in jobs])
+    bad = []
+    for i, (t, st, g) in enumerate(zip(ts, sts, recs)):
+        if not same[i]:
+            continue
+        if (digest(t.cpu().numpy()), st.passes, st.lowerings) != (
+                g["output_sha256"], g["passes"], g["lowerings"]) or not st.converged:
+            bad.append(i)
+        assert st.examinations >= g["examinations"], i
+    assert not bad, f"{len(bad)} images differ from the oracle, first {bad[:8]}"

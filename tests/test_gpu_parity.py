@@ -252,6 +252,34 @@ def test_graph_mode_matches_oracle():
             assert_same(F, 5, 0, t.cpu().numpy(), st)
 
 
+def test_graph_cache_tells_calls_apart():
+    """Replayed graphs are keyed by everything the recorded launches bake in:
+    a one-image call followed by a two-image batch with the same tile count,
+    and a u8 then a u16 image of the same size on a bit-flag shape (one
+    launch per pixel type), each checked against the oracle."""
+    one = synth.gen_blobs(64, 128, 901, nblobs=6, sigma=(2.0, 8.0))
+    pair = [synth.gen_blobs(64, 64, 902 + i, nblobs=6, sigma=(2.0, 8.0)) for i in range(2)]
+    say("case graph key: image counts")
+    with thin.Context(graph=True) as ctx:
+        for rep in range(2):
+            t = torch.from_numpy(one.copy()).cuda()
+            st = ctx.run(t, 5, 0)
+            assert_same(one, 5, 0, t.cpu().numpy(), st)
+            ts = [torch.from_numpy(F.copy()).cuda() for F in pair]
+            sts = ctx.run_batch(ts, [5, 5], [0, 0])
+            for F, t, st in zip(pair, ts, sts):
+                assert_same(F, 5, 0, t.cpu().numpy(), st)
+    u8 = synth.gen_blobs(256, 256, 903, np.uint8, nblobs=10, sigma=(3.0, 12.0))
+    u16 = synth.gen_blobs(256, 256, 904, np.uint16, nblobs=10, sigma=(3.0, 12.0))
+    say("case graph key: pixel types")
+    with thin.Context(graph=True, tile=64, steps_per_round=16, threads=256, variant=3) as ctx:
+        for rep in range(2):
+            for F, lam in ((u8, 20), (u16, 300)):
+                t = torch.from_numpy(F.copy()).cuda()
+                st = ctx.run(t, lam, 0)
+                assert_same(F, lam, 0, t.cpu().numpy(), st)
+
+
 def test_autotune_leaves_inputs_and_results_unchanged():
     Fs = [synth.gen_blobs(80 + 40 * i, 120 + 30 * i, 500 + i, np.uint16 if i % 2 else np.uint8)
           for i in range(6)]

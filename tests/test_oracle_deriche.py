@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import deriche
+from paper_1603_09180_amd import synth
 
 ALPHAS = [0.5, 1.0, 2.0]
 
@@ -115,3 +116,31 @@ def test_float32_decision_close_to_float64():
 def test_quantize_rounds_half_to_even_and_clamps():
     m = np.array([0.0, 0.5, 1.5, 2.5, 254.4, 254.5, 300.0], np.float32)
     assert deriche.quantize(m, 1.0).tolist() == [0, 0, 2, 2, 254, 254, 255]
+
+
+def test_quantize_reference_margins():
+    """The float64 decision of D5 and its distance from the rounding
+    boundaries, on hand-picked values (gain 1): rint halves go to even, the
+    clamp at the top has no boundary."""
+    mag = np.array([0.0, 0.2, 0.5, 1.5, 2.49, 254.6, 255.4, 255.5, 300.0])
+    q, margin = deriche.quantize_reference(mag, 1.0, np.uint8)
+    assert q.tolist() == [0, 0, 0, 2, 2, 255, 255, 255, 255]
+    assert np.allclose(margin[:7], [0.5, 0.3, 0.0, 0.0, 0.01, 0.1, 0.1])
+    assert margin[7] == 0.0 and np.isinf(margin[8])
+    q16, _ = deriche.quantize_reference(np.array([70000.0, 12.5]), 1.0, np.uint16)
+    assert q16.tolist() == [65535, 12]
+
+
+def test_float32_decision_differs_only_near_boundaries():
+    """The float32 gradient image differs from the float64 decision only
+    where the float64 value sits within the stated tolerance of a rounding
+    boundary (the bound the GPU test applies)."""
+    F = synth.gen_blobs(120, 90, 3)
+    _, _, m64 = deriche.gradient(F, 1.0)
+    q32 = deriche.gradient_image(F, 1.0, 12.0)
+    q64, margin = deriche.quantize_reference(m64, 12.0)
+    scale = max(float(m64.max()), float(F.max()), 1.0)
+    tol = 2e-5 * scale * 12.0 + 2.0 ** -23 * (m64 * 12.0 + 1.0)
+    diff = q32.astype(int) - q64.astype(int)
+    assert np.all((diff == 0) | (margin <= tol))
+    assert np.abs(diff).max() <= 1
