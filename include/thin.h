@@ -156,6 +156,27 @@ int thin_create(thin_ctx** out, const thin_config* cfg);
 int thin_run(thin_ctx* ctx, void* image, int64_t h, int64_t w, int32_t dtype,
              uint32_t lambda, int32_t adjacency, thin_stats* stats);
 
+/* thin_run for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same arguments, result, statistics and errors as thin_run, but every
+ * scratch buffer (the ping-pong twin, per-tile state and change bitmaps,
+ * tile queues, counters, the image descriptor) is carved out of a static
+ * device array of 64 MiB that the library holds on each GPU it runs on until
+ * the process ends, so the call makes no hipMalloc, hipFree or other
+ * allocating call (thin_create set up what it needs: the array's device
+ * address on the context's device and the host counter snapshots).  An image
+ * whose scratch does not fit (its twin plus about a quarter byte per pixel of
+ * tile state: square u8 images up to 7296x7296, u16 up to 5453x5453) is
+ * refused with THIN_ENOMEM and left untouched.
+ * Runs on the tiled engine only (THIN_EINVAL for other engine settings);
+ * THIN_FLAG_GRAPH and THIN_FLAG_PROFILE are ignored.  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other host
+ * threads, other contexts, other streams) race and must be serialised by
+ * the caller.  Each call clears the parts of the array that must start at
+ * zero. */
+int thin_run_noalloc(thin_ctx* ctx, void* image, int64_t h, int64_t w, int32_t dtype,
+                     uint32_t lambda, int32_t adjacency, thin_stats* stats);
+
 /* The lambda-skeleton of one image (section 2.2, the algorithm box: lower
  * the lambda-deletable, not lambda-end points until stability; section 2.1
  * for peaks, end points and alpha-).  Arguments, conventions, order of

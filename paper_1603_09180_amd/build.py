@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libthin.so")
 
-SOURCES = ["thin_kernels.hip", "gradient.hip", "thin_runtime.cpp", "topo_table.cpp"]
+SOURCES = ["thin_kernels.hip", "gradient.hip", "noalloc.hip", "thin_runtime.cpp",
+           "topo_table.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -136,6 +136,16 @@ constexpr int kGradPlanes = 8;
 hipError_t launch_gradient(hipStream_t stream, const void* src, int64_t src_pitch, int src_dtype,
                            int h, int w, float* scratch, void* dst, int64_t dst_pitch,
                            int dst_dtype, float* mag, GradCoef co, float gain);
+// Writes descriptor d to *dst on `stream` (a kernel argument, so no host
+// buffer has to outlive the call).
+hipError_t launch_set_desc(hipStream_t stream, ImgDev* dst, const ImgDev& d);
+
+// The static scratch array of the no-allocation entry point (noalloc.hip):
+// its size, and the device address of the copy on `device`, looked up once
+// per device (the caller makes `device` current).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+hipError_t noalloc_scratch(int device, void** out);
+
 // Every compiled shape: writes up to cap of them to out, returns the count.
 int compiled_shapes(TileShape* out, int cap);
 int round_blocks_per_cu(TileShape s);

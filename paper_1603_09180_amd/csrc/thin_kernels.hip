@@ -184,6 +184,11 @@ __global__ void k_init_state(ImgCnt* cnt, int nimg, int32_t* tile_last, int ntil
     if (tile_last && i < 2 * ntiles) tile_last[i] = -1;
 }
 
+__global__ void k_set_desc(ImgDev* dst, ImgDev d)
+{
+    if (threadIdx.x == 0) *dst = d;
+}
+
 __global__ void k_advance(int32_t* round_base, int n)
 {
     if (threadIdx.x == 0) *round_base += n;
@@ -1526,6 +1531,12 @@ hipError_t launch_init_state(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t*
     const int n = max(max(nimg, 2 * ntiles), 3);
     hipLaunchKernelGGL(k_init_state, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
                        stream, cnt, nimg, tile_last, ntiles, hist_round, wl);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_desc(hipStream_t stream, ImgDev* dst, const ImgDev& d)
+{
+    hipLaunchKernelGGL(k_set_desc, dim3(1), dim3(64), 0, stream, dst, d);
     return hipGetLastError();
 }
 

@@ -157,6 +157,7 @@ struct thin_ctx {
     std::map<std::pair<int, int>, TileShape> tuned;
 
     int last_launches = 0;         // round launches of the last tiled run
+    void* noalloc = nullptr;       // this device's copy of the static scratch array
 
     std::string last_error;
 };
@@ -1012,6 +1013,67 @@ int autotune(thin_ctx* ctx, const thin_image* imgs, int n, int reps, thin_tune_r
     return THIN_OK;
 }
 
+// thin_run_noalloc: one image on the tiled engine with every scratch buffer
+// carved out of this device's copy of the static scratch array (no device or
+// pinned allocation; the counter snapshots were allocated by thin_create).
+int run_noalloc(thin_ctx* ctx, const thin_image& im, thin_stats* stats)
+{
+    int rc = validate(ctx, im);
+    if (rc) return rc;
+    if (im.h < 3 || im.w < 3) {
+        if (stats) fill_stats(stats, ImgCnt{}, 0, 0, true);
+        return THIN_OK;
+    }
+    if (ctx->engine != THIN_ENGINE_TILED)
+        return fail(ctx, THIN_EINVAL, "thin_run_noalloc runs on the tiled engine only");
+    if (!ctx->noalloc || ctx->h_snap_cap < 1)
+        return fail(ctx, THIN_EDEVICE, "the static scratch array was not set up by thin_create");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const TileShape shape = choose_shape(ctx, im.h * im.w, 1);
+    if (!thin::tile_shape_supported(shape))
+        return fail(ctx, THIN_EINVAL, "unsupported tile shape %dx%d k=%d", shape.th, shape.tw, shape.k);
+    const uint64_t ty = (uint64_t)((im.h + shape.th - 1) / shape.th);
+    const uint64_t tx = (uint64_t)((im.w + shape.tw - 1) / shape.tw);
+    const uint64_t ntiles = ty * tx;
+    const uint64_t bpp = im.dtype == THIN_U8 ? 1 : 2;
+    // Layout, each part 256-byte aligned: descriptor, counters, 16 words,
+    // per-tile state, change bitmaps and rounds, tile queues, then the twin.
+    uint64_t off = 0;
+    auto take = [&](uint64_t bytes) {
+        const uint64_t at = off;
+        off += (bytes + 255) & ~uint64_t(255);
+        return at;
+    };
+    const uint64_t o_imgs = take(sizeof(ImgDev));
+    const uint64_t o_cnt = take(sizeof(ImgCnt));
+    const uint64_t o_small = take(16 * sizeof(int32_t));
+    const uint64_t o_last = take(2 * ntiles * sizeof(int32_t));
+    const uint64_t o_bits = take(2 * ntiles * (uint64_t)thin::history_words(shape) * sizeof(uint32_t));
+    const uint64_t o_hround = take(2 * ntiles * sizeof(int32_t));
+    const uint64_t o_list = take(2 * ntiles * sizeof(int32_t));
+    const uint64_t o_meta = take((4 + ntiles) * sizeof(int32_t));
+    const uint64_t o_twin = take((uint64_t)im.h * (uint64_t)pitch_of(im) * bpp);
+    if (off > thin::kNoAllocScratchBytes || ntiles > (uint64_t)INT_MAX / 2)
+        return fail(ctx, THIN_ENOMEM,
+                    "a %lldx%lld image needs %llu bytes of scratch; thin_run_noalloc has %llu",
+                    (long long)im.h, (long long)im.w, (unsigned long long)off,
+                    (unsigned long long)thin::kNoAllocScratchBytes);
+    char* base = static_cast<char*>(ctx->noalloc);
+    TiledBufs b{};
+    b.imgs = reinterpret_cast<ImgDev*>(base + o_imgs);
+    b.cnt = reinterpret_cast<ImgCnt*>(base + o_cnt);
+    b.tile_img = nullptr;  // one image: the kernels never read the tile map
+    b.tile_last = reinterpret_cast<int32_t*>(base + o_last);
+    b.hist_bits = reinterpret_cast<uint32_t*>(base + o_bits);
+    b.hist_round = reinterpret_cast<int32_t*>(base + o_hround);
+    b.wl_list = reinterpret_cast<int32_t*>(base + o_list);
+    b.wl_meta = reinterpret_cast<int32_t*>(base + o_meta);
+    b.small = reinterpret_cast<int32_t*>(base + o_small);
+    const ImgDev d = describe_tiled(im, shape, base + o_twin, 0, 0, steps_cap(ctx));
+    HIP_TRY(ctx, thin::launch_set_desc(ctx->stream, b.imgs, d));
+    return drive_tiled(ctx, shape, &d, 1, (int)ntiles, b, nullptr, stats, false);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------- ABI
@@ -1077,6 +1139,11 @@ int thin_create(thin_ctx** out, const thin_config* cfg)
                 rc = THIN_EDEVICE;
                 break;
             }
+        if (rc != THIN_OK) break;
+        // Counter snapshots for up to 64 images now, so that the no-allocation
+        // entry point finds them; and this device's copy of its scratch array.
+        if (ensure_snap(ctx, 64) != THIN_OK) { rc = THIN_ENOMEM; break; }
+        if (thin::noalloc_scratch(c.device, &ctx->noalloc) != hipSuccess) { rc = THIN_EDEVICE; break; }
     } while (0);
     if (rc != THIN_OK) {
         (void)hipGetLastError();
@@ -1099,6 +1166,21 @@ int thin_run(thin_ctx* ctx, void* image, int64_t h, int64_t w, int32_t dtype, ui
     im.lambda = lambda;
     im.adjacency = adjacency;
     return run_images(ctx, &im, 1, stats);
+}
+
+int thin_run_noalloc(thin_ctx* ctx, void* image, int64_t h, int64_t w, int32_t dtype,
+                     uint32_t lambda, int32_t adjacency, thin_stats* stats)
+{
+    if (!ctx) return THIN_EINVAL;
+    thin_image im{};
+    im.image = image;
+    im.h = h;
+    im.w = w;
+    im.pitch_elems = w;
+    im.dtype = dtype;
+    im.lambda = lambda;
+    im.adjacency = adjacency;
+    return run_noalloc(ctx, im, stats);
 }
 
 int thin_skeleton(thin_ctx* ctx, void* image, int64_t h, int64_t w, int32_t dtype,

@@ -24,7 +24,7 @@ THIN_FLAG_PROFILE = 1
 THIN_FLAG_GRAPH = 2
 
 EXPORTED = [
-    "thin_create", "thin_run", "thin_skeleton", "thin_run_batch", "thin_serve_admit",
+    "thin_create", "thin_run", "thin_run_noalloc", "thin_skeleton", "thin_run_batch", "thin_serve_admit",
     "thin_serve_step",
     "thin_destroy", "thin_strerror", "thin_last_error", "thin_profile", "thin_topology_table",
     "thin_autotune", "thin_gradient", "thin_gradient_coefficients",
@@ -117,6 +117,8 @@ def load_library(path: str = LIB_PATH):
     lib.thin_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
                              ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32, P(thin_stats)]
     lib.thin_run.restype = ctypes.c_int
+    lib.thin_run_noalloc.argtypes = lib.thin_run.argtypes
+    lib.thin_run_noalloc.restype = ctypes.c_int
     lib.thin_skeleton.argtypes = lib.thin_run.argtypes
     lib.thin_skeleton.restype = ctypes.c_int
     lib.thin_run_batch.argtypes = [ctypes.c_void_p, P(thin_image), ctypes.c_int32, P(thin_stats)]
@@ -168,6 +170,13 @@ def thin_run(ctx, image_ptr: int, h: int, w: int, dtype: int, lam: int, adjacenc
     return load_library().thin_run(ctx, ctypes.c_void_p(image_ptr), h, w, dtype,
                                    ctypes.c_uint32(lam), adjacency,
                                    ctypes.byref(stats) if stats is not None else None)
+
+
+def thin_run_noalloc(ctx, image_ptr: int, h: int, w: int, dtype: int, lam: int, adjacency: int,
+                     stats: thin_stats | None = None) -> int:
+    return load_library().thin_run_noalloc(ctx, ctypes.c_void_p(image_ptr), h, w, dtype,
+                                           ctypes.c_uint32(lam), adjacency,
+                                           ctypes.byref(stats) if stats is not None else None)
 
 
 def thin_skeleton(ctx, image_ptr: int, h: int, w: int, dtype: int, lam: int, adjacency: int,
