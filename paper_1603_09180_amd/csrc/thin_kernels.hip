@@ -1021,8 +1021,9 @@ struct BTile {
     static constexpr int WAVE_WORDS = WAVE_ROWS * LWW;
     static constexpr int LIST_ELEMS = (NCELL + 1) & ~1;
     // LDS bytes behind the flag pointer: 4 pending bitmaps, 4 lowered
-    // bitmaps, the step's list and two list lengths
-    static constexpr int DIRTY_ELEMS = 32 * CLASS_WORDS + 2 * LIST_ELEMS + 8;
+    // bitmaps, a ring of 8 list lengths and 8 "lowered" flags (by step),
+    // 4 "has seeds" flags (by class), the step's list
+    static constexpr int DIRTY_ELEMS = 32 * CLASS_WORDS + 32 + 16 + 2 * LIST_ELEMS;
     static constexpr int WPR = TW >= 32 ? TW / 32 : 1;
     static constexpr int RWW = (RW + 31) / 32;
     static constexpr int BITS_WORDS = SEED ? TH * WPR : 1;
@@ -1077,8 +1078,10 @@ struct BTile {
         (void)t0;  // a multiple of 4: step tau has class tau mod 4
         uint32_t* s_db = reinterpret_cast<uint32_t*>(s_flags);           // [4][LAT_H][LWW]
         uint32_t* s_dl = s_db + 4 * CLASS_WORDS;                         // [4][LAT_H][LWW]
-        uint16_t* s_list = reinterpret_cast<uint16_t*>(s_dl + 4 * CLASS_WORDS);
-        int* s_total = reinterpret_cast<int*>(s_list + LIST_ELEMS);  // [2], by step parity
+        int* s_total = reinterpret_cast<int*>(s_dl + 4 * CLASS_WORDS);   // [8]: step tau & 7
+        uint8_t* s_low = reinterpret_cast<uint8_t*>(s_total + 8);        // [8]: step tau & 7
+        uint8_t* s_seeds = s_low + 8;                                    // [4]: class
+        uint16_t* s_list = reinterpret_cast<uint16_t*>(s_seeds + 8);
         const int ry0 = gy0 - K, rx0 = gx0 - K;
         const bool seeded = SEED && sd != nullptr && sd->r > 0;
         if (tid == 0) {
@@ -1089,7 +1092,11 @@ struct BTile {
         if constexpr (SEED)
             for (int i = tid; i < TH * WPR; i += NT) s_bits[i] = 0u;
         for (int i = tid; i < 4 * CLASS_WORDS; i += NT) s_dl[i] = 0u;
-        if (tid == 0) s_total[0] = s_total[1] = 0;
+        if (tid < 8) {
+            s_total[tid] = 0;
+            s_low[tid] = 0;
+            s_seeds[tid] = seeded ? 0 : 1;
+        }
         if (!seeded) {
             for (int i = tid; i < 4 * CLASS_WORDS; i += NT) s_db[i] = valid_bits(i % LWW);
         } else if constexpr (SEED) {
@@ -1135,7 +1142,9 @@ struct BTile {
                     }
                     half[hw] = even_bits(m >> sj);
                 }
-                s_db[i] = (half[0] | (half[1] << 16)) & valid_bits(j);
+                const uint32_t word = (half[0] | (half[1] << 16)) & valid_bits(j);
+                s_db[i] = word;
+                if (word) s_seeds[c] = 1;
             }
             __syncthreads();
         }
@@ -1148,6 +1157,31 @@ struct BTile {
         int my_exams = 0;                // candidates characterised (thread 0 counts the lists)
         for (int tau = 0; tau < nsteps; ++tau) {
             const int c = tau & 3, si = c >> 1, sj = c & 1;
+            // A step's candidates come from the residency's seeds (first 4
+            // steps) and from pixels lowered during the 4 steps before it.
+            // When neither exists the step cannot lower anything; once 4
+            // steps in a row are quiet and the seeds are used up, no later
+            // step of the residency can either.  The flags were written
+            // before the last barrier, so every thread takes the same
+            // branch.  A skipped step still clears the two ring slots it
+            // owns (its "lowered" flag, and the list length of step tau + 4,
+            // whose last readers were at step tau - 4).
+            {
+                const uint64_t lw = *reinterpret_cast<const uint64_t*>(s_low);
+                const int sh = 8 * ((tau + 4) & 7);  // slots tau-4 .. tau-1, in ring order
+                const uint64_t rot = sh ? ((lw >> sh) | (lw << (64 - sh))) : lw;
+                const uint64_t recent = rot & 0xFFFFFFFFull;
+                const bool quiet = recent == 0ull && !(tau < 4 && s_seeds[c]);
+                if (quiet) {
+                    if (tau >= 4) break;
+                    if (tid == 0) {
+                        s_low[tau & 7] = 0;
+                        s_total[(tau + 4) & 7] = 0;
+                    }
+                    continue;
+                }
+            }
+            if (tid == 0) s_low[tau & 7] = 0;
             // Exact region after tau steps, clipped to the image interior,
             // as lattice rows a (region row 2a + si) and columns b (2b + sj).
             const int r_lo = max(tau + 1, 1 - ry0), r_hi = min(RH - 2 - tau, d.h - 2 - ry0);
@@ -1200,7 +1234,7 @@ struct BTile {
             const int incl = wave_inclusive_sum(cnt);
             const int wave_total = __builtin_amdgcn_readlane(incl, 63);
             int base = 0;
-            if (lane == 63 && wave_total) base = atomicAdd(&s_total[tau & 1], wave_total);
+            if (lane == 63 && wave_total) base = atomicAdd(&s_total[tau & 7], wave_total);
             base = __builtin_amdgcn_readlane(base, 63);
             if (take) {
                 int off = base + incl - cnt;
@@ -1212,12 +1246,12 @@ struct BTile {
                 }
             }
             __syncthreads();
-            const int total = s_total[tau & 1];
+            const int total = s_total[tau & 7];
             if (tid == 0) {
-                s_total[(tau + 1) & 1] = 0;
+                s_total[(tau + 4) & 7] = 0;
                 my_exams += total;
             }
-            bool inner = false;
+            bool inner = false, lowered = false;
             for (int i = tid; i < total; i += NT) {
                 const int cell = s_list[i];
                 const int a = cell >> 8, b = cell & 0xFF;
@@ -1229,6 +1263,7 @@ struct BTile {
                 uint32_t alpha;
                 if (decide<true>(v, nbv, lut, lambda, alpha)) {
                     p[0] = (E)alpha;
+                    lowered = true;
                     atomicOr(&s_dl[c * CLASS_WORDS + a * LWW + (b >> 5)], 1u << (b & 31));
                     if (lr >= K && lr < K + TH && lc >= K && lc < K + TW) {
                         ++my_count;
@@ -1242,6 +1277,8 @@ struct BTile {
                     }
                 }
             }
+            // one store per wave (the lanes would all write the same byte)
+            if (__ballot(lowered) != 0ull && lane == 0) s_low[tau & 7] = 1;
             if (inner) my_last = tau;
             __syncthreads();
         }
@@ -1273,6 +1310,25 @@ using TileOf = typename std::conditional<
     typename std::conditional<VAR == kVarBits || VAR == kVarBitsSeeded,
                               BTile<TH, TW, K, NT, VAR == kVarBitsSeeded, E>,
                               Tile<TH, TW, K, NT, VAR == kVarSeeded>>::type>::type;
+
+// Waves per SIMD that the LDS of one residency of T allows (blocks per CU
+// times waves per block over the 4 SIMDs).  The large bit-flag tiles of the
+// batched path ask the compiler to fit their registers to it, so that
+// register growth never costs them a resident block (their register needs
+// sit just under that budget); the other shapes need more registers than
+// their LDS occupancy would leave them, and ask for nothing (1).
+template <typename T, int NT, int TH, int VAR>
+constexpr int lds_waves_per_eu()
+{
+    if constexpr (!(TH >= 128 && (VAR == kVarBits || VAR == kVarBitsSeeded))) return 1;
+    constexpr int lds = (int)sizeof(typename T::Elem) * T::IMG_ELEMS + T::DIRTY_ELEMS +
+                        4 * T::BITS_WORDS + 4 * T::CW_WORDS + (int)sizeof(TopoEntry) * 256 + 64;
+    constexpr int by_lds = (160 * 1024) / lds;
+    constexpr int by_threads = 2048 / NT;
+    constexpr int blocks = by_lds < by_threads ? by_lds : by_threads;
+    constexpr int w = (blocks < 1 ? 1 : blocks) * (NT / 64) / 4;
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
 
 // ----------------------------------------------------------------- k_round
 
@@ -1367,37 +1423,43 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
     const int count = T::run(v, gy0, gx0, t0, nsteps, src, dst, s_img, s_dirty, s_bits, s_cw,
                              var_seeded(VAR) ? &sd : nullptr, s_lut, s_count, s_last, s_exam,
                              tid, last_tau);
-    if (tid == 0) {
-        atomicAdd(&cnt[slot].tile_rounds, 1ull);
-        atomicAdd(&cnt[slot].examinations, (unsigned long long)*s_exam);
-        if (last_tau >= 0) {
-            __hip_atomic_store(&st[1], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            atomicAdd(&cnt[slot].lowerings, (unsigned long long)count);
-            atomicMax(&cnt[slot].last_step, t0 + last_tau);
-            if (wl.list != nullptr) enqueue(wl, g, round + 1);
+    // Counters and the tiles the next round must visit, from the lanes of
+    // wave 0 in parallel (one lane per tile of the 3x3 tile block), so the
+    // block's next tile is not held up by a chain of dependent atomics.
+    if (tid < 64) {
+        if (tid == 0) {
+            atomicAdd(&cnt[slot].tile_rounds, 1ull);
+            atomicAdd(&cnt[slot].examinations, (unsigned long long)*s_exam);
+            if (last_tau >= 0) {
+                __hip_atomic_store(&st[1], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                atomicAdd(&cnt[slot].lowerings, (unsigned long long)count);
+                atomicMax(&cnt[slot].last_step, t0 + last_tau);
+            }
         }
         // Lowered during the last 4 steps: the 3x3 tile block must run the next
         // round (a tile whose whole block was quiet for 4 steps cannot change
-        // within the next K <= tile-side steps).
+        // within the next K <= tile-side steps).  Lowered earlier: the tile
+        // itself is visited again (to copy itself across the ping-pong pair).
         if (last_tau >= nsteps - 4) {
-            for (int dy = -1; dy <= 1; ++dy) {
-                const int y = ty + dy;
-                if (y < 0 || y >= d->tiles_y) continue;
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int x = tx + dx;
-                    if (x < 0 || x >= d->tiles_x) continue;
+            if (tid < 9) {
+                const int y = ty + tid / 3 - 1, x = tx + tid % 3 - 1;
+                if (y >= 0 && y < d->tiles_y && x >= 0 && x < d->tiles_x) {
                     __hip_atomic_fetch_max(&tile_state[2 * (d->state0 + y * d->tiles_x + x)],
                                            r + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (wl.list != nullptr) enqueue(wl, d->tile0 + y * d->tiles_x + x, round + 1);
                 }
             }
+        } else if (last_tau >= 0 && tid == 0 && wl.list != nullptr) {
+            enqueue(wl, g, round + 1);
         }
     }
     return 1;
 }
 
 template <int TH, int TW, int K, int NT, int VAR, typename E>
-__global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
+__global__ __attribute__((amdgpu_flat_work_group_size(1, NT),
+                          amdgpu_waves_per_eu(lds_waves_per_eu<TileOf<TH, TW, K, NT, VAR, E>, NT, TH, VAR>())))
+void k_round(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                                               const int32_t* __restrict__ tile_img,
                                               int32_t* tile_last, int ntiles, int round,
                                               const TopoEntry* __restrict__ lut_g,
@@ -1437,7 +1499,9 @@ __global__ __launch_bounds__(NT) void k_round(const ImgDev* __restrict__ imgs, I
 // barrier has proved those reads complete.
 
 template <int TH, int TW, int K, int NT, int VAR, typename E>
-__global__ __launch_bounds__(NT) void k_coop(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
+__global__ __attribute__((amdgpu_flat_work_group_size(1, NT),
+                          amdgpu_waves_per_eu(lds_waves_per_eu<TileOf<TH, TW, K, NT, VAR, E>, NT, TH, VAR>())))
+void k_coop(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
                                              const int32_t* __restrict__ tile_img,
                                              int32_t* tile_last, int ntiles,
                                              const TopoEntry* __restrict__ lut_g, int32_t* active,

@@ -176,13 +176,45 @@ def test_dirty_equals_plain(adj):
             assert b.examinations <= (F.shape[0] - 2) * (F.shape[1] - 2) * a.passes
 
 
+def test_dirty_equals_plain_ten_thousand_images():
+    """10^4 seeded small images, each with its own lambda (0..40) and
+    pairing: the dirty-pixel sweep gives the plain sweep's image, passes and
+    lowerings, and never examines more than the plain sweep does."""
+    rng = np.random.default_rng(2026)
+    for k, F in enumerate(_small_images(91, 10_000, max_side=18, levels=12)):
+        lam = int(rng.integers(0, 41))
+        adj = ADJS[k & 1]
+        a = oracle.sweep(F, lam, adj)
+        b = oracle.sweep_dirty(F, lam, adj)
+        assert np.array_equal(a.image, b.image), k
+        assert (a.passes, a.lowerings) == (b.passes, b.lowerings), k
+        assert b.examinations <= (F.shape[0] - 2) * (F.shape[1] - 2) * a.passes
+
+
 def test_dirty_equals_plain_on_workloads():
-    for job in (synth.blobs_128(),):
-        F = job.image()
-        a = oracle.sweep(F, job.lam, job.adj)
-        b = oracle.sweep_dirty(F, job.lam, job.adj)
-        assert np.array_equal(a.image, b.image)
-        assert (a.passes, a.lowerings) == (b.passes, b.lowerings)
+    """The two sweeps agree on the single-image workloads: the 128x128 blob
+    image (lambda 0) directly, and the 512x512 ridge image (lambda 20) through
+    the stored digest of the dirty sweep's result (the plain sweep takes
+    about half a minute there)."""
+    import hashlib
+    import json
+    import os
+
+    job = synth.blobs_128()
+    F = job.image()
+    a = oracle.sweep(F, job.lam, job.adj)
+    b = oracle.sweep_dirty(F, job.lam, job.adj)
+    assert np.array_equal(a.image, b.image)
+    assert (a.passes, a.lowerings) == (b.passes, b.lowerings)
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                    "full_size.json")))["ridges_512"]
+    job = synth.ridges_512()
+    F = job.image()
+    if hashlib.sha256(F.tobytes()).hexdigest() != g["input_sha256"]:
+        pytest.skip("the generator does not reproduce the stored ridge image here")
+    a = oracle.sweep(F, job.lam, job.adj)
+    assert hashlib.sha256(np.ascontiguousarray(a.image).tobytes()).hexdigest() == g["output_sha256"]
+    assert (a.passes, a.lowerings) == (g["passes"], g["lowerings"])
 
 
 @pytest.mark.parametrize("adj", ADJS)
