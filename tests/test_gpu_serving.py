@@ -181,6 +181,32 @@ def test_replay_poisson_arrivals():
     _check_oracle(items, outs, rep.stats)
 
 
+def test_replay_from_host_memory():
+    """Requests in pinned host memory: copied in on a second stream when they
+    arrive, copied back as they retire; every host result equals the oracle,
+    and a large u8 and u16 image ride along with the small ones."""
+    items = _mix(seed=93, n=30)
+    items.append((synth.gen_blobs(1500, 1100, 9301, synth.U8), 20, 0))
+    items.append((synth.gen_blobs(1200, 900, 9302, synth.U16), 300, 0))
+    rng = np.random.default_rng(6)
+    arrivals = np.cumsum(rng.exponential(1.0 / 3000.0, size=len(items)))
+    reqs = []
+    for i, ((F, lam, adj), a) in enumerate(zip(items, arrivals)):
+        host = torch.from_numpy(F.copy()).pin_memory()
+        out = torch.empty(host.shape, dtype=host.dtype, pin_memory=True)
+        dev = torch.empty(host.shape, dtype=host.dtype, device="cuda")
+        reqs.append(serve.Request(tag=i, image=dev, lam=lam, adj=adj, arrival=float(a),
+                                  host_in=host, host_out=out))
+    copy_stream = torch.cuda.Stream()
+    say("case serving replay from host memory")
+    with thin.Context() as ctx:
+        rep = serve.replay(ctx, reqs, rounds_per_step=2, copy_stream=copy_stream)
+    torch.cuda.synchronize()
+    assert rep.images == len(items) and (rep.latencies_s > 0).all()
+    outs = [r.host_out.numpy() for r in reqs]
+    _check_oracle(items, outs, rep.stats)
+
+
 def test_device_blob_generator():
     a = synth.gen_blobs_device(300, 200, 11, synth.U16)
     b = synth.gen_blobs_device(300, 200, 11, synth.U16)
