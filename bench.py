@@ -41,6 +41,13 @@ sys.path.insert(0, ROOT)
 METRIC = ("Mpixel/s and images/s to convergence (bit-exact), batched vs plain; "
           "p50/p99 latency")
 HBM_PEAK_GBS = 8000.0
+# 32-bit integer vector operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# integer operations of one characterisation and lowering as the method
+# defines it: 8 compares for the upper mask, 1 table lookup (T+, T--,
+# destructible), the lambda test (1 subtraction, 8 compares, 4 for the
+# component count), alpha- (8 selects, 7 maxima), 3 to select and write
+OPS_PER_EXAMINATION = 40
 
 
 def _percentile(xs, q):
@@ -423,6 +430,13 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, tune=True, graph=False,
     px_passes = sum(F.size * st.passes for F, st in zip(Fs, stats))
     avg_launch_s = kernel_ms / 1e3 / max(launches, 1)
     achieved = alg_one / max(launches, 1) / avg_launch_s / 1e9 if kernel_ms > 0 else None
+    # the ALU roofline in the same streaming-equivalent units (one
+    # characterisation per pixel-pass), and in the method's own work (the
+    # oracle's examinations X)
+    ops_launch = OPS_PER_EXAMINATION * px_passes / max(launches, 1)
+    achieved_tops = ops_launch / avg_launch_s / 1e12 if kernel_ms > 0 else None
+    method_tops = (OPS_PER_EXAMINATION * x_method / (kernel_ms / 1e3) / 1e12
+                   if kernel_ms > 0 else None)
     traffic = _traffic_for("k_round", "batch_512")
     out = {
         "metric": METRIC,
@@ -452,16 +466,24 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, tune=True, graph=False,
         "bit_exact_images": sum(same_input),
         "streaming_equiv_frac_of_hbm": round(alg_one * steps / elapsed / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": {
-            "bound": "hbm", "kernel": "k_round",
-            "achieved": round(achieved, 2) if achieved else None,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "bound": "alu", "kernel": "k_round",
+            "achieved": round(achieved_tops, 3) if achieved_tops else None,
+            "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s",
+            "frac": round(achieved_tops / ALU_PEAK_TOPS, 4) if achieved_tops else None,
             "traffic": traffic,
             "launches_per_step": launches,
             "avg_launch_us": round(avg_launch_s * 1e6, 3),
-            "alg_bytes_per_launch": round(alg_one / max(launches, 1), 1),
+            "alg_ops_per_launch": round(ops_launch, 1),
+            "ops_per_pixel_pass": OPS_PER_EXAMINATION,
+            "hbm": {"achieved": round(achieved, 2) if achieved else None, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+                    "alg_bytes_per_launch": round(alg_one / max(launches, 1), 1)},
+            "method_work_frac": round(method_tops / ALU_PEAK_TOPS, 4) if method_tops else None,
             "timing": "HIP events around every round launch on the library's stream, in a "
                       "second pass over the same batch",
+            "units": "streaming-equivalent: one characterisation (40 integer ops) and one read "
+                     "and write of the pixel per pixel-pass (H*W*P); method_work_frac counts "
+                     "the oracle's examinations X instead",
         },
         # the method's own work (oracle dirty-pixel sweep, stored per image)
         # against the streaming H*W*P pixel-passes and the kernels' own count

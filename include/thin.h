@@ -86,11 +86,15 @@ enum {
     THIN_ENGINE_TILED = 1,    /* one launch per round of LDS tiles (several parity steps per
                                  residency, stable tiles skipped); the host checks convergence */
     THIN_ENGINE_STEP = 2,     /* one parity step per launch over global memory (simple, slow) */
-    THIN_ENGINE_PERSIST = 3,  /* reserved (a persistent work-queue engine; not available:
-                                 calls return THIN_EINVAL) */
-    THIN_ENGINE_COOP = 4      /* one cooperative launch for the whole run: the tiled engine's
+    /* 3 is not used (permanently unavailable: thin_create refuses it) */
+    THIN_ENGINE_COOP = 4,     /* one cooperative launch for the whole run: the tiled engine's
                                  rounds separated by grid-wide barriers; convergence decided
                                  on the device */
+    THIN_ENGINE_WORKLIST = 5  /* pixel work lists (the re-examination rule of section 2.2):
+                                 one block per image runs every parity step, examining only
+                                 the candidates whose 3x3 changed since their last examination
+                                 (thin_stats.examinations then equals the sequential
+                                 dirty-pixel sweep's count); sides up to 131070 */
 };
 
 typedef struct thin_ctx thin_ctx;
@@ -107,13 +111,22 @@ typedef struct thin_config {
     int32_t threads;            /* with tile: threads per tile, 0 = first compiled choice */
     int32_t variant;            /* with tile and threads: residency variant (thin_tune_result) */
     int32_t reserved;
+    const char* tune_cache;     /* NULL, or the path of a text file of autotuned shapes: read at
+                                   thin_create (entries for this device's architecture only),
+                                   and thin_autotune adds or replaces its result there; the
+                                   string is copied */
 } thin_config;
 
 /* thin_config.flags */
 enum {
     THIN_FLAG_PROFILE = 1,      /* time every round kernel with HIP events (see thin_profile) */
-    THIN_FLAG_GRAPH = 2         /* tiled engine: replay chunks of rounds as HIP graphs
+    THIN_FLAG_GRAPH = 2,        /* tiled engine: replay chunks of rounds as HIP graphs
                                    (ignored while THIN_FLAG_PROFILE is set) */
+    THIN_FLAG_TAIL = 4          /* tiled engine: hand a single image's convergence tail to the
+                                   pixel work-list kernel once the image (at most 512x512
+                                   pixels) lowers fewer than 2048 pixels per round; results are
+                                   identical, and on MI355X it is measured slower than staying
+                                   on the tiles, so it is off by default */
 };
 
 typedef struct thin_profile_info {
@@ -233,7 +246,10 @@ typedef struct thin_tune_result {
  * them: the caller's buffers are left untouched) once with every compiled
  * tile shape, re-times the fastest few `reps` times, and makes the fastest
  * the context's shape for later work lists of the same size class (total
- * pixels and pixels per image, each rounded down to a power of two).  The
+ * pixels and pixels per image, each rounded down to a power of two).  With
+ * thin_config.tune_cache set, the choice is also written to that file under
+ * the device's architecture name (e.g. gfx950) and size class, so later
+ * contexts on the same architecture start from it.  The
  * results of every shape are identical; only the time differs.  The copies
  * are freed before the call returns.  out may be NULL.  Returns THIN_OK,
  * THIN_EINVAL (bad arguments, nothing to tune), THIN_ENOMEM or

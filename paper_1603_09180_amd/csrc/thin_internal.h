@@ -136,6 +136,40 @@ constexpr int kGradPlanes = 8;
 hipError_t launch_gradient(hipStream_t stream, const void* src, int64_t src_pitch, int src_dtype,
                            int h, int w, float* scratch, void* dst, int64_t dst_pitch,
                            int dst_dtype, float* mag, GradCoef co, float gain);
+// Pixel work-list engine (k_worklist): one block per image runs parity
+// steps one after the other, examining only the candidates whose 3x3
+// changed since their last examination.
+struct WlImg {
+    void* image;          // the image state, updated in place
+    const void* prev;     // init 1: the state one tiled round earlier (same pitch)
+    uint32_t* gbits;      // pending bitmaps in global memory (4 * lh * lww words), or null
+    int64_t pitch;        // row pitch in elements
+    int32_t h, w;
+    int32_t dtype;        // 1 = u8, 2 = u16
+    uint32_t lambda;
+    int32_t adj;          // table index (adjacency + 2 * operator)
+    int32_t step0;        // global index of the first step to run
+    int32_t max_steps;    // step cap (global index), INT32_MAX if none
+    int32_t init;         // 0: every interior candidate pending; 1: those whose 3x3 differs
+                          // between image and prev
+    int32_t slot;         // counter slot
+    int32_t pad;
+};
+constexpr int kWlThreads = 1024;
+constexpr int kWlListCap = 2048;      // entries per candidate list
+constexpr int kWlLdsWords = 8192;     // pending-bitmap words kept in LDS (32 KiB)
+// Pending-bitmap words of an image (4 classes of ceil(h/2) rows of
+// ceil(ceil(w/2)/32) words).
+inline int64_t wl_bitmap_words(int64_t h, int64_t w)
+{
+    return 4 * ((h + 1) / 2) * ((((w + 1) / 2) + 31) / 32);
+}
+// One block per image; steps_out[i] receives the global index one past the
+// last step image i ran.  gbits selects the variant with the pending bitmaps
+// in global memory (every image of the launch must have gbits set then).
+hipError_t launch_worklist(hipStream_t stream, const WlImg* imgs, int nimg, int dtype,
+                           bool gbits, ImgCnt* cnt, const TopoEntry* lut, int32_t* steps_out);
+
 // Writes descriptor d to *dst on `stream` (a kernel argument, so no host
 // buffer has to outlive the call).
 hipError_t launch_set_desc(hipStream_t stream, ImgDev* dst, const ImgDev& d);

@@ -1436,12 +1436,53 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
                 atomicMax(&cnt[slot].last_step, t0 + last_tau);
             }
         }
-        // Lowered during the last 4 steps: the 3x3 tile block must run the next
-        // round (a tile whose whole block was quiet for 4 steps cannot change
-        // within the next K <= tile-side steps).  Lowered earlier: the tile
-        // itself is visited again (to copy itself across the ping-pong pair).
+        // Lowered during the last 4 steps: the tile and those of its 8
+        // neighbours within reach must run the next round.  Only pixels next
+        // to a pixel lowered during the last 4 steps can be pending, and a
+        // change travels at most one pixel per step, so in the next K steps
+        // a neighbour's interior can change only if one of those lowerings
+        // lies within K of it; a tile none of whose 3x3 tile block is within
+        // reach cannot change (K <= tile side).  The seeded variants know
+        // where those lowerings are (their change bitmap): wave 0 takes the
+        // bounding box and spares the neighbours beyond K + 1 (one pixel of
+        // margin); the others ask the whole 3x3 block.  Lowered earlier: the
+        // tile itself is visited again (to copy itself across the ping-pong
+        // pair).
         if (last_tau >= nsteps - 4) {
-            if (tid < 9) {
+            uint32_t ask = 0x1FFu;  // bit 3 (dy + 1) + (dx + 1)
+            if constexpr (var_seeded(VAR)) {
+                if (nsteps >= 4) {
+                    int rmin = TH, rmax = -1, cmin = TW, cmax = -1;
+                    for (int i = tid; i < TH * T::WPR; i += 64) {
+                        const uint32_t w = s_bits[i];
+                        if (!w) continue;
+                        const int row = i / T::WPR, c0 = 32 * (i - row * T::WPR);
+                        rmin = min(rmin, row);
+                        rmax = max(rmax, row);
+                        cmin = min(cmin, c0 + __ffs(w) - 1);
+                        cmax = max(cmax, c0 + 31 - __clz(w));
+                    }
+#pragma unroll
+                    for (int o = 32; o >= 1; o >>= 1) {
+                        rmin = min(rmin, __shfl_xor(rmin, o));
+                        rmax = max(rmax, __shfl_xor(rmax, o));
+                        cmin = min(cmin, __shfl_xor(cmin, o));
+                        cmax = max(cmax, __shfl_xor(cmax, o));
+                    }
+                    if (rmax >= 0) {
+                        constexpr int REACH = K + 1;
+                        const bool up = rmin <= REACH, down = rmax >= TH - 1 - REACH;
+                        const bool left = cmin <= REACH, right = cmax >= TW - 1 - REACH;
+                        const uint32_t rows = (up ? 1u : 0u) | 2u | (down ? 4u : 0u);
+                        const uint32_t cols = (left ? 1u : 0u) | 2u | (right ? 4u : 0u);
+                        ask = 0u;
+#pragma unroll
+                        for (int q = 0; q < 9; ++q)
+                            if (((rows >> (q / 3)) & 1u) && ((cols >> (q % 3)) & 1u)) ask |= 1u << q;
+                    }
+                }
+            }
+            if (tid < 9 && ((ask >> tid) & 1u)) {
                 const int y = ty + tid / 3 - 1, x = tx + tid % 3 - 1;
                 if (y >= 0 && y < d->tiles_y && x >= 0 && x < d->tiles_x) {
                     __hip_atomic_fetch_max(&tile_state[2 * (d->state0 + y * d->tiles_x + x)],
@@ -1587,6 +1628,254 @@ hipError_t launch_round_t(hipStream_t stream, const ImgDev* imgs, ImgCnt* cnt,
     return hipGetLastError();
 }
 
+// -------------------------------------------------------------- k_worklist
+//
+// The re-examination rule of section 2.2 as explicit per-class candidate
+// lists.  A candidate is pending when a pixel of its 3x3 (itself included)
+// was lowered since its last examination; the visit of its class examines
+// every pending candidate of that class once and clears it; a lowered pixel
+// marks its 3x3 pending (one bit per lattice cell and class, set with an
+// atomic so each cell enters its class's list once).  The class being
+// visited receives no marks from its own step except the lowered pixels
+// themselves, which become the next list of that class.  Started with every
+// interior candidate pending, the engine examines exactly the candidates
+// the sequential dirty-pixel sweep examines.
+//
+// Lists hold (lattice row << 16) | lattice column and live in LDS; a list
+// that overflows is dropped and its class's next visit scans the bitmap
+// instead (the bitmap is always exact).  The pending bitmaps stay in LDS when
+// they fit, else in global memory.  One block of kWlThreads threads per image;
+// two barriers per step.
+
+// Pending-bitmap access of k_worklist.  In global memory the words are read
+// and written with device-scope atomics, which go to L2 like the bit-setting
+// atomics, so no wave reads a stale copy from its CU's L1.
+template <bool GBITS>
+__device__ __forceinline__ uint32_t wl_load(uint32_t* w)
+{
+    if constexpr (GBITS) return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *w;
+}
+template <bool GBITS>
+__device__ __forceinline__ void wl_store(uint32_t* w, uint32_t v)
+{
+    if constexpr (GBITS) __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *w = v;
+}
+template <bool GBITS>
+__device__ __forceinline__ uint32_t wl_or(uint32_t* w, uint32_t m)
+{
+    if constexpr (GBITS) return __hip_atomic_fetch_or(w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return atomicOr(w, m);
+}
+template <bool GBITS>
+__device__ __forceinline__ void wl_and(uint32_t* w, uint32_t m)
+{
+    if constexpr (GBITS) __hip_atomic_fetch_and(w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else atomicAnd(w, m);
+}
+
+template <typename E, bool GBITS>
+__global__ __launch_bounds__(kWlThreads) void k_worklist(const WlImg* __restrict__ imgs,
+                                                       ImgCnt* cnt,
+                                                       const TopoEntry* __restrict__ lut_g,
+                                                       int32_t* steps_out)
+{
+    __shared__ TopoEntry s_lut[256];
+    __shared__ uint32_t s_lbits[GBITS ? 1 : kWlLdsWords];
+    __shared__ uint32_t s_list[5][kWlListCap];
+    __shared__ int s_n[5], s_ovf[5], s_map[4];
+    __shared__ int s_j, s_low, s_quiet, s_step, s_last;
+    __shared__ unsigned long long s_exam, s_lowsum;
+    const int tid = threadIdx.x;
+    const WlImg im = imgs[blockIdx.x];
+    E* img = static_cast<E*>(im.image);
+    const int64_t P = im.pitch;
+    const int H = im.h, W = im.w;
+    const int LH = (H + 1) / 2, LW = (W + 1) / 2, LWW = (LW + 31) / 32, CW = LH * LWW;
+    uint32_t* bits = GBITS ? im.gbits : s_lbits;
+    for (int i = tid; i < 256; i += kWlThreads) s_lut[i] = lut_g[im.adj * 256 + i];
+    if (tid < 5) {
+        s_n[tid] = 0;
+        s_ovf[tid] = 1;   // first visit of each class scans its bitmap
+    }
+    if (tid < 4) s_map[tid] = tid;
+    if (tid == 0) {
+        s_j = 4;
+        s_low = 0;
+        s_quiet = 0;
+        s_step = im.step0;
+        s_last = -1;
+        s_exam = 0ull;
+        s_lowsum = 0ull;
+    }
+    // Initial pending sets.  Cell (a, b) of class (si, sj) is pixel
+    // (2a + si, 2b + sj); only interior pixels are ever pending.  With init 1
+    // a candidate is pending when a pixel of its 3x3 differs from the state
+    // one tiled round earlier: a pixel-change bitmap (1 bit per pixel, rows of
+    // DW words) is built first, in the list storage while it is unused when
+    // it fits there.
+    const int DW = (W + 31) / 32;
+    uint32_t* dmap = &s_list[0][0];
+    const bool dfast = im.init == 1 && H * DW <= 5 * kWlListCap;
+    if (dfast) {
+        const E* prev = static_cast<const E*>(im.prev);
+        for (int wd = tid; wd < H * DW; wd += kWlThreads) {
+            const int y = wd / DW, x0 = 32 * (wd - y * DW);
+            const E* ra = img + (int64_t)y * P + x0;
+            const E* rb = prev + (int64_t)y * P + x0;
+            const int nx = min(32, W - x0);
+            uint32_t m = 0u;
+            for (int t = 0; t < nx; ++t) m |= (uint32_t)(ra[t] != rb[t]) << t;
+            dmap[wd] = m;
+        }
+        __syncthreads();
+    }
+    for (int wd = tid; wd < 4 * CW; wd += kWlThreads) {
+        const int c = wd / CW, rem = wd - c * CW;
+        const int a = rem / LWW, j0 = 32 * (rem - a * LWW);
+        const int i = 2 * a + (c >> 1);
+        uint32_t word = 0u;
+        if (i >= 1 && i <= H - 2) {
+            for (int t = 0; t < 32; ++t) {
+                const int j = 2 * (j0 + t) + (c & 1);
+                if (j < 1 || j > W - 2) continue;
+                bool pend = true;
+                if (dfast) {
+                    pend = false;
+                    for (int di = -1; di <= 1; ++di) {
+                        const uint32_t* row = dmap + (i + di) * DW;
+                        for (int dj = -1; dj <= 1; ++dj) {
+                            const int x = j + dj;
+                            pend |= ((row[x >> 5] >> (x & 31)) & 1u) != 0u;
+                        }
+                    }
+                } else if (im.init == 1) {
+                    const E* prev = static_cast<const E*>(im.prev);
+                    pend = false;
+                    for (int di = -1; di <= 1 && !pend; ++di)
+                        for (int dj = -1; dj <= 1; ++dj) {
+                            const int64_t o = (int64_t)(i + di) * P + (j + dj);
+                            if (img[o] != prev[o]) {
+                                pend = true;
+                                break;
+                            }
+                        }
+                }
+                if (pend) word |= 1u << t;
+            }
+        }
+        wl_store<GBITS>(&bits[wd], word);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+
+    const uint32_t lambda = im.lambda;
+    unsigned long long my_exam = 0ull;
+    for (;;) {
+        const int t = s_step;
+        if (s_quiet >= 4 || t >= im.max_steps) break;
+        const int c = t & 3, si = c >> 1, sj = c & 1;
+        const int L = s_map[c], J = s_j;
+        const bool scan = s_ovf[L] != 0;
+        const int n = scan ? CW : min(s_n[L], kWlListCap);
+        int my_low = 0;
+        // one candidate (or, scanning, one bitmap word) per iteration
+        for (int k = tid; k < n; k += kWlThreads) {
+            uint32_t cells, wbase;
+            int a, b0;
+            if (scan) {
+                cells = wl_load<GBITS>(&bits[c * CW + k]);
+                if (!cells) continue;
+                wl_store<GBITS>(&bits[c * CW + k], 0u);   // no other thread touches it this step
+                a = k / LWW;
+                b0 = 32 * (k - a * LWW);
+                wbase = c * CW + k;
+            } else {
+                const uint32_t e = s_list[L][k];
+                a = (int)(e >> 16);
+                const int b = (int)(e & 0xFFFFu);
+                b0 = b & ~31;
+                cells = 1u << (b & 31);
+                wbase = c * CW + a * LWW + (b >> 5);
+                wl_and<GBITS>(&bits[wbase], ~cells);
+            }
+            uint32_t relower = 0u;
+            while (cells) {
+                const int bit = __ffs(cells) - 1;
+                cells &= cells - 1u;
+                ++my_exam;
+                const int i = 2 * a + si, j = 2 * (b0 + bit) + sj;
+                E* p = img + (int64_t)i * P + j;
+                const uint32_t v = p[0];
+                const uint32_t nbv[8] = {p[1], p[-P + 1], p[-P], p[-P - 1],
+                                         p[-1], p[P - 1], p[P], p[P + 1]};
+                uint32_t alpha;
+                if (!decide<false>(v, nbv, s_lut, lambda, alpha)) continue;
+                p[0] = (E)alpha;
+                ++my_low;
+                relower |= 1u << bit;
+                // itself: the next list of this class
+                const int pos = atomicAdd(&s_n[J], 1);
+                if (pos < kWlListCap) s_list[J][pos] = ((uint32_t)a << 16) | (uint32_t)(b0 + bit);
+                else s_ovf[J] = 1;
+                // its 8 neighbours (other classes), interior only
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int di = q < 3 ? -1 : (q < 5 ? 0 : 1);
+                    const int dj = q < 3 ? q - 1 : (q == 3 ? -1 : (q == 4 ? 1 : q - 6));
+                    const int y = i + di, x = j + dj;
+                    if (y < 1 || y > H - 2 || x < 1 || x > W - 2) continue;
+                    const int cy = ((y & 1) << 1) | (x & 1);
+                    const int ay = y >> 1, by = x >> 1;
+                    const uint32_t m = 1u << (by & 31);
+                    const uint32_t old = wl_or<GBITS>(&bits[cy * CW + ay * LWW + (by >> 5)], m);
+                    if (old & m) continue;
+                    const int lk = s_map[cy];
+                    const int pp = atomicAdd(&s_n[lk], 1);
+                    if (pp < kWlListCap) s_list[lk][pp] = ((uint32_t)ay << 16) | (uint32_t)by;
+                    else s_ovf[lk] = 1;
+                }
+            }
+            if (relower) {
+                // lowered cells are pending again for their next visit
+                wl_or<GBITS>(&bits[wbase], relower);
+            }
+        }
+        if (my_low) atomicAdd(&s_low, my_low);
+        // The image and (in global memory) the bitmaps are shared through
+        // memory: every wave's writes must be complete before the barrier.
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (tid == 0) {
+            // the lowered pixels of this step are the next list of class c
+            s_map[c] = J;
+            s_j = L;
+            s_n[L] = 0;
+            s_ovf[L] = 0;
+            if (s_low) {
+                s_quiet = 0;
+                s_last = t - im.step0;
+                s_lowsum += (unsigned long long)s_low;
+            } else {
+                ++s_quiet;
+            }
+            s_low = 0;
+            s_step = t + 1;
+        }
+        __syncthreads();
+    }
+    if (my_exam) atomicAdd(&s_exam, my_exam);
+    __syncthreads();
+    if (tid == 0) {
+        ImgCnt* ct = cnt + im.slot;
+        atomicAdd(&ct->lowerings, s_lowsum);
+        atomicAdd(&ct->examinations, s_exam);
+        if (s_last >= 0) atomicMax(&ct->last_step, im.step0 + s_last);
+        steps_out[blockIdx.x] = s_step;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_init_state(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t* tile_last,
@@ -1595,6 +1884,21 @@ hipError_t launch_init_state(hipStream_t stream, ImgCnt* cnt, int nimg, int32_t*
     const int n = max(max(nimg, 2 * ntiles), 3);
     hipLaunchKernelGGL(k_init_state, dim3((n + kThreads - 1) / kThreads), dim3(kThreads), 0,
                        stream, cnt, nimg, tile_last, ntiles, hist_round, wl);
+    return hipGetLastError();
+}
+
+hipError_t launch_worklist(hipStream_t stream, const WlImg* imgs, int nimg, int dtype,
+                           bool gbits, ImgCnt* cnt, const TopoEntry* lut, int32_t* steps_out)
+{
+    if (nimg <= 0) return hipSuccess;
+    const dim3 grid(nimg), block(kWlThreads);
+    if (dtype == 1) {
+        if (gbits) hipLaunchKernelGGL((k_worklist<uint8_t, true>), grid, block, 0, stream, imgs, cnt, lut, steps_out);
+        else hipLaunchKernelGGL((k_worklist<uint8_t, false>), grid, block, 0, stream, imgs, cnt, lut, steps_out);
+    } else {
+        if (gbits) hipLaunchKernelGGL((k_worklist<uint16_t, true>), grid, block, 0, stream, imgs, cnt, lut, steps_out);
+        else hipLaunchKernelGGL((k_worklist<uint16_t, false>), grid, block, 0, stream, imgs, cnt, lut, steps_out);
+    }
     return hipGetLastError();
 }
 
@@ -1658,6 +1962,8 @@ hipError_t launch_step(hipStream_t stream, const ImgDev* img_host, const ImgDev*
     X(128, 128, 16, 512, 3) \
     X(128, 128, 16, 512, 4) \
     X(128, 128, 32, 512, 4) \
+    X(128, 128, 8, 512, 4)  \
+    X(128, 128, 24, 512, 4) \
     X(64, 64, 16, 512, 2)   \
     X(32, 32, 16, 512, 2)   \
     X(16, 16, 8, 256, 2)    \

@@ -106,7 +106,6 @@ struct Retired {
 };
 
 constexpr int kServeSlots = 1 << 14;          // resident images at most
-constexpr int kMaxChunk = 4;                  // rounds launched between counter read-backs
 constexpr uint64_t kServeDefaultBudget = 1ull << 30;
 
 }  // namespace
@@ -123,6 +122,7 @@ struct thin_ctx {
     TopoEntry* d_lut = nullptr;
     uint64_t allocated = 0;        // bytes of scratch currently held
     DevBuf twin, imgs, cnt, tile_img, tile_last, small, hist_bits, hist_round, wl_list, wl_meta;
+    DevBuf wl_imgs, wl_bits;       // pixel work-list engine: descriptors, global pending bitmaps
     DevBuf grad;                   // gradient front-end scratch (8 floats per pixel)
     ImgCnt* h_snap[2] = {nullptr, nullptr};   // pinned snapshots of the counters
     size_t h_snap_cap = 0;
@@ -155,8 +155,12 @@ struct thin_ctx {
 
     // autotuned shapes by size class (log2 total pixels, log2 pixels per image)
     std::map<std::pair<int, int>, TileShape> tuned;
+    std::string tune_cache;        // file of tuned shapes ("" = none)
+    std::string arch;              // device architecture name, e.g. gfx950
 
     int last_launches = 0;         // round launches of the last tiled run
+    int last_tail_steps = 0;       // steps its work-list tail ran (0: none)
+    bool tail = false;             // hand single small images' tails to the work-list kernel
     void* noalloc = nullptr;       // this device's copy of the static scratch array
 
     std::string last_error;
@@ -337,6 +341,51 @@ std::pair<int, int> size_class(int64_t total_pixels, int64_t images)
     return {floor_log2(total_pixels), floor_log2(total_pixels / std::max<int64_t>(images, 1))};
 }
 
+// Tune cache file: one line per entry,
+//   <arch> <log2 total pixels> <log2 pixels per image> <th> <tw> <k> <threads> <variant> <ms>
+// Lines of other architectures, or naming shapes this build does not have,
+// are ignored when reading and kept when writing.
+void load_tune_cache(thin_ctx* ctx)
+{
+    if (ctx->tune_cache.empty()) return;
+    FILE* f = fopen(ctx->tune_cache.c_str(), "r");
+    if (!f) return;
+    char arch[64];
+    int a, b;
+    TileShape sh{};
+    double ms;
+    while (fscanf(f, "%63s %d %d %d %d %d %d %d %lf", arch, &a, &b, &sh.th, &sh.tw, &sh.k, &sh.nt,
+                  &sh.var, &ms) == 9)
+        if (ctx->arch == arch && thin::tile_shape_supported(sh)) ctx->tuned[{a, b}] = sh;
+    fclose(f);
+}
+
+void save_tune_cache(const thin_ctx* ctx, std::pair<int, int> cls, TileShape sh, double ms)
+{
+    if (ctx->tune_cache.empty()) return;
+    std::vector<std::string> keep;
+    if (FILE* f = fopen(ctx->tune_cache.c_str(), "r")) {
+        char line[256];
+        while (fgets(line, sizeof line, f)) {
+            char arch[64];
+            int a, b;
+            if (sscanf(line, "%63s %d %d", arch, &a, &b) == 3 && ctx->arch == arch &&
+                a == cls.first && b == cls.second)
+                continue;  // replaced below
+            keep.push_back(line);
+        }
+        fclose(f);
+    }
+    const std::string tmp = ctx->tune_cache + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (const std::string& l : keep) fputs(l.c_str(), f);
+    fprintf(f, "%s %d %d %d %d %d %d %d %.4f\n", ctx->arch.c_str(), cls.first, cls.second, sh.th,
+            sh.tw, sh.k, sh.nt, sh.var, ms);
+    fclose(f);
+    std::rename(tmp.c_str(), ctx->tune_cache.c_str());
+}
+
 TileShape choose_shape(const thin_ctx* ctx, int64_t total_pixels, int64_t images)
 {
     if (ctx->forced.th) return ctx->forced;
@@ -416,6 +465,35 @@ int chunk_graph(thin_ctx* ctx, const std::vector<uint64_t>& key, F record, hipGr
     return THIN_OK;
 }
 
+int launch_worklists(thin_ctx* ctx, std::vector<thin::WlImg>& wl, std::vector<int32_t>& steps,
+                     ImgCnt* d_cnt);
+
+// A single image lowering fewer than this many pixels per round (counted
+// over the last chunk of rounds) has its remaining steps run by the pixel
+// work-list kernel; THIN_TAIL_RATE overrides it (tuning).
+// Rounds launched between counter read-backs at most (the host reads them one
+// chunk behind, so a run stops at most one chunk past stability);
+// THIN_MAX_CHUNK overrides it (tuning).
+int max_chunk()
+{
+    static int c = 0;
+    if (c == 0) {
+        const char* e = getenv("THIN_MAX_CHUNK");
+        c = e ? std::max(1, atoi(e)) : 4;
+    }
+    return c;
+}
+
+double tail_rate()
+{
+    static double r = -1.0;
+    if (r < 0.0) {
+        const char* e = getenv("THIN_TAIL_RATE");
+        r = e ? atof(e) : 2048.0;
+    }
+    return r;
+}
+
 // Device memory one tiled run works in (context-owned buffers, or carved out
 // of the library's static scratch array by the no-allocation entry point).
 struct TiledBufs {
@@ -490,6 +568,15 @@ int drive_tiled(thin_ctx* ctx, TileShape shape, const ImgDev* h_imgs, int nimg, 
         return thin::launch_advance(st, d_round, count);
     };
     int rc;
+    // Tail hand-over: one image whose pending bitmaps fit the work-list
+    // kernel's LDS, on the default tiled path.
+    const bool tail_ok = allocate && ctx->tail && nimg == 1 && !use_graph &&
+                         ctx->engine == THIN_ENGINE_TILED && h_imgs[0].h <= 131070 &&
+                         h_imgs[0].w <= 131070 &&
+                         thin::wl_bitmap_words(h_imgs[0].h, h_imgs[0].w) <= thin::kWlLdsWords;
+    bool handover = false;
+    unsigned long long prev_low = 0;
+    int prev_rounds = -1;
     while (!done) {
         const int n = std::min(chunk, rounds_cap - launched);
         if (use_graph) {
@@ -540,13 +627,68 @@ int drive_tiled(thin_ctx* ctx, TileShape shape, const ImgDev* h_imgs, int nimg, 
         if (launched >= rounds_cap) break;
         if (pending >= 0) {
             HIP_TRY(ctx, hipEventSynchronize(ctx->ev[pending]));
-            if (all_done(ctx->h_snap[pending], pending_rounds)) done = true;
+            if (all_done(ctx->h_snap[pending], pending_rounds)) {
+                done = true;
+            } else if (tail_ok) {
+                const unsigned long long low = ctx->h_snap[pending][0].lowerings;
+                if (prev_rounds >= 0 && pending_rounds > prev_rounds &&
+                    (double)(low - prev_low) < tail_rate() * (pending_rounds - prev_rounds)) {
+                    handover = true;
+                    done = true;
+                }
+                prev_low = low;
+                prev_rounds = pending_rounds;
+            }
         }
         pending = slot;
         pending_rounds = launched;
-        chunk = std::min(chunk * 2, kMaxChunk);
+        chunk = std::min(chunk * 2, max_chunk());
     }
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    // steps each image has run
+    std::vector<int> steps_done(nimg);
+    for (int i = 0; i < nimg; ++i)
+        steps_done[i] = (int)std::min<int64_t>((int64_t)launched * K, h_imgs[i].max_steps);
+    if (handover && steps_done[0] < h_imgs[0].max_steps) {
+        // The remaining steps on the pixel work lists, in place on the
+        // current state buf[launched & 1]; a candidate starts pending when a
+        // pixel of its 3x3 changed during the last round (a superset of the
+        // candidates the next steps need, so the result is unchanged).
+        const ImgDev& d = h_imgs[0];
+        thin::WlImg w{};
+        w.image = d.buf[launched & 1];
+        w.prev = d.buf[(launched + 1) & 1];
+        w.pitch = d.pitch;
+        w.h = d.h;
+        w.w = d.w;
+        w.dtype = d.dtype;
+        w.lambda = d.lambda;
+        w.adj = d.adj;
+        w.step0 = steps_done[0];
+        w.max_steps = d.max_steps;
+        w.init = 1;
+        w.slot = d.slot;
+        std::vector<thin::WlImg> wl{w};
+        std::vector<int32_t> st;
+        if (profile) {
+            while (ctx->prof_ev.size() < ev_used + 2) {
+                hipEvent_t e;
+                HIP_TRY(ctx, hipEventCreate(&e));
+                ctx->prof_ev.push_back(e);
+            }
+            HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used], ctx->stream));
+        }
+        if ((rc = launch_worklists(ctx, wl, st, b.cnt))) return rc;
+        if (profile) {
+            HIP_TRY(ctx, hipEventRecord(ctx->prof_ev[ev_used + 1], ctx->stream));
+            HIP_TRY(ctx, hipEventSynchronize(ctx->prof_ev[ev_used + 1]));
+            ev_used += 2;
+        }
+        steps_done[0] = st[0];
+        ctx->last_tail_steps = st[0] - w.step0;
+    } else {
+        ctx->last_tail_steps = 0;
+    }
     HIP_TRY(ctx, hipMemcpyAsync(ctx->h_snap[0], b.cnt, sizeof(ImgCnt) * nimg,
                                 hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -575,9 +717,8 @@ int drive_tiled(thin_ctx* ctx, TileShape shape, const ImgDev* h_imgs, int nimg, 
     bool limited = false;
     for (int i = 0; i < nimg; ++i) {
         const ImgDev& d = h_imgs[i];
-        const int steps = (int)std::min<int64_t>((int64_t)launched * K, d.max_steps);
         thin_stats st;
-        fill_stats(&st, fin[i], steps, d.max_steps, false);
+        fill_stats(&st, fin[i], steps_done[i], d.max_steps, false);
         if (!st.converged) limited = true;
         if (stats) stats[src_index ? src_index[i] : i] = st;
     }
@@ -854,6 +995,111 @@ int run_step_engine(thin_ctx* ctx, const thin_image* ims, const std::vector<int>
     return limited ? fail(ctx, THIN_ELIMIT, "max_passes reached before stability") : THIN_OK;
 }
 
+// ------------------------------------------------------- pixel work-list engine
+
+// Runs k_worklist on the images `wl` (descriptors on the host, counters in
+// slots 0..n-1 already cleared), one launch per pixel type and bitmap home;
+// steps[i] receives one past the last global step image i ran.
+int launch_worklists(thin_ctx* ctx, std::vector<thin::WlImg>& wl, std::vector<int32_t>& steps,
+                     ImgCnt* d_cnt)
+{
+    const int n = (int)wl.size();
+    int rc;
+    uint64_t gwords = 0;
+    for (const thin::WlImg& w : wl)
+        if (thin::wl_bitmap_words(w.h, w.w) > thin::kWlLdsWords) gwords += thin::wl_bitmap_words(w.h, w.w);
+    if ((rc = ensure(ctx, ctx->wl_imgs, sizeof(thin::WlImg) * n + sizeof(int32_t) * n + 256))) return rc;
+    if (gwords && (rc = ensure(ctx, ctx->wl_bits, sizeof(uint32_t) * gwords))) return rc;
+    uint64_t goff = 0;
+    for (thin::WlImg& w : wl) {
+        const int64_t words = thin::wl_bitmap_words(w.h, w.w);
+        w.gbits = nullptr;
+        if (words > thin::kWlLdsWords) {
+            w.gbits = static_cast<uint32_t*>(ctx->wl_bits.ptr) + goff;
+            goff += (uint64_t)words;
+        }
+    }
+    // group by (pixel type, bitmap home): each group is one launch
+    std::vector<thin::WlImg> order;
+    std::vector<int> index;
+    std::vector<std::pair<int, int>> groups;  // (first, count)
+    for (int dt = 1; dt <= 2; ++dt)
+        for (int g = 0; g < 2; ++g) {
+            const int first = (int)order.size();
+            for (int i = 0; i < n; ++i)
+                if (wl[i].dtype == dt && (wl[i].gbits != nullptr) == (g == 1)) {
+                    order.push_back(wl[i]);
+                    index.push_back(i);
+                }
+            groups.push_back({first, (int)order.size() - first});
+        }
+    thin::WlImg* d_wl = static_cast<thin::WlImg*>(ctx->wl_imgs.ptr);
+    int32_t* d_steps = reinterpret_cast<int32_t*>(d_wl + n);
+    HIP_TRY(ctx, hipMemcpyAsync(d_wl, order.data(), sizeof(thin::WlImg) * n, hipMemcpyHostToDevice,
+                                ctx->stream));
+    for (int k = 0; k < 4; ++k) {
+        const int first = groups[k].first, cnt = groups[k].second;
+        if (!cnt) continue;
+        HIP_TRY(ctx, thin::launch_worklist(ctx->stream, d_wl + first, cnt, 1 + k / 2, (k & 1) != 0,
+                                           d_cnt, ctx->d_lut, d_steps + first));
+    }
+    std::vector<int32_t> st(n);
+    HIP_TRY(ctx, hipMemcpyAsync(st.data(), d_steps, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    steps.assign(n, 0);
+    for (int i = 0; i < n; ++i) steps[index[i]] = st[i];
+    return THIN_OK;
+}
+
+thin::WlImg describe_worklist(const thin_image& im, int slot, int max_steps)
+{
+    thin::WlImg w{};
+    w.image = im.image;
+    w.pitch = pitch_of(im);
+    w.h = (int32_t)im.h;
+    w.w = (int32_t)im.w;
+    w.dtype = im.dtype;
+    w.lambda = im.lambda;
+    w.adj = table_index(im);
+    w.step0 = 0;
+    w.max_steps = max_steps;
+    w.init = 0;
+    w.slot = slot;
+    return w;
+}
+
+int run_worklist(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work,
+                 thin_stats* stats)
+{
+    const int n = (int)work.size();
+    for (int i : work)
+        if (ims[i].h > 131070 || ims[i].w > 131070)
+            return fail(ctx, THIN_EINVAL, "the work-list engine takes sides up to 131070");
+    int rc;
+    if ((rc = ensure(ctx, ctx->cnt, sizeof(ImgCnt) * n))) return rc;
+    if ((rc = ensure_snap(ctx, n))) return rc;
+    ImgCnt* d_cnt = static_cast<ImgCnt*>(ctx->cnt.ptr);
+    HIP_TRY(ctx, thin::launch_init_state(ctx->stream, d_cnt, n, nullptr, 0, nullptr,
+                                         thin::WorkList{}));
+    const int max_steps = steps_cap(ctx);
+    std::vector<thin::WlImg> wl;
+    for (int k = 0; k < n; ++k) wl.push_back(describe_worklist(ims[work[k]], k, max_steps));
+    std::vector<int32_t> steps;
+    if ((rc = launch_worklists(ctx, wl, steps, d_cnt))) return rc;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_snap[0], d_cnt, sizeof(ImgCnt) * n, hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    bool limited = false;
+    for (int k = 0; k < n; ++k) {
+        thin_stats st;
+        fill_stats(&st, ctx->h_snap[0][k], steps[k], max_steps, false);
+        if (!st.converged) limited = true;
+        if (stats) stats[work[k]] = st;
+    }
+    return limited ? fail(ctx, THIN_ELIMIT, "max_passes reached before stability") : THIN_OK;
+}
+
 int run_images(thin_ctx* ctx, const thin_image* ims, int n, thin_stats* stats)
 {
     if (!ctx) return THIN_EINVAL;
@@ -873,8 +1119,7 @@ int run_images(thin_ctx* ctx, const thin_image* ims, int n, thin_stats* stats)
     if (work.empty()) return THIN_OK;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if (ctx->engine == THIN_ENGINE_STEP) return run_step_engine(ctx, ims, work, stats);
-    if (ctx->engine == THIN_ENGINE_PERSIST)
-        return fail(ctx, THIN_EINVAL, "the persistent engine is not available");
+    if (ctx->engine == THIN_ENGINE_WORKLIST) return run_worklist(ctx, ims, work, stats);
     if (ctx->engine == THIN_ENGINE_COOP) return run_coop(ctx, ims, work, stats);
     return run_tiled(ctx, ims, work, stats);
 }
@@ -995,6 +1240,7 @@ int autotune(thin_ctx* ctx, const thin_image* imgs, int n, int reps, thin_tune_r
             res.ms = timed[b].first;
             res.candidates = (int32_t)timed.size();
             ctx->tuned[cls] = best;
+            save_tune_cache(ctx, cls, best, res.ms);
         } else if (prev_shape.th) {
             ctx->tuned[cls] = prev_shape;
         }
@@ -1086,7 +1332,7 @@ int thin_create(thin_ctx** out, const thin_config* cfg)
     *out = nullptr;
     thin_config c{};
     if (cfg) c = *cfg;
-    if (c.engine < 0 || c.engine > THIN_ENGINE_COOP) return THIN_EINVAL;
+    if (c.engine < 0 || c.engine > THIN_ENGINE_WORKLIST || c.engine == 3) return THIN_EINVAL;
     if ((c.tile != 0) != (c.steps_per_round != 0)) return THIN_EINVAL;
     TileShape forced{0, 0, 0, 0, 0};
     if (c.tile && c.threads) {
@@ -1118,6 +1364,7 @@ int thin_create(thin_ctx** out, const thin_config* cfg)
     ctx->max_passes = c.max_passes;
     ctx->forced = forced;
     ctx->profile = (c.flags & THIN_FLAG_PROFILE) != 0;
+    ctx->tail = (c.flags & THIN_FLAG_TAIL) != 0;
     ctx->graph = (c.flags & THIN_FLAG_GRAPH) != 0;
     int rc = THIN_OK;
     do {
@@ -1126,6 +1373,16 @@ int thin_create(thin_ctx** out, const thin_config* cfg)
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c.device) == hipSuccess &&
             cus > 0)
             ctx->num_cus = cus;
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, c.device) == hipSuccess) {
+            // "gfx950:sramecc+:xnack-" -> "gfx950"
+            std::string name = prop.gcnArchName;
+            ctx->arch = name.substr(0, name.find(':'));
+        }
+        if (c.tune_cache) {
+            ctx->tune_cache = c.tune_cache;
+            load_tune_cache(ctx);
+        }
         TopoEntry table[thin::kTables * 256];
         for (int t = 0; t < thin::kTables; ++t)
             thin::build_topology_table(t & 1, t >> 1, table + 256 * t);
@@ -1219,7 +1476,8 @@ int thin_destroy(thin_ctx* ctx)
     DevBuf* bufs[] = {&ctx->twin,       &ctx->imgs,        &ctx->cnt,        &ctx->tile_img,
                       &ctx->tile_last,  &ctx->small,      &ctx->wl_list,    &ctx->wl_meta,
                       &ctx->hist_bits,  &ctx->hist_round,  &ctx->serve_twin, &ctx->serve_state,
-                      &ctx->serve_cnt,  &ctx->serve_imgs,  &ctx->serve_tile_img, &ctx->grad};
+                      &ctx->serve_cnt,  &ctx->serve_imgs,  &ctx->serve_tile_img, &ctx->grad,
+                      &ctx->wl_imgs,    &ctx->wl_bits};
     for (DevBuf* b : bufs)
         if (b->ptr) (void)hipFree(b->ptr);
     if (ctx->d_lut) (void)hipFree(ctx->d_lut);
@@ -1358,7 +1616,7 @@ int thin_serve_admit(thin_ctx* ctx, const thin_image* img, uint64_t tag)
     if (!img) return fail(ctx, THIN_EINVAL, "NULL image descriptor");
     int rc = validate(ctx, *img);
     if (rc) return rc;
-    if (ctx->engine == THIN_ENGINE_STEP || ctx->engine == THIN_ENGINE_PERSIST)
+    if (ctx->engine == THIN_ENGINE_STEP || ctx->engine == THIN_ENGINE_WORKLIST)
         return fail(ctx, THIN_EINVAL, "serving runs on the tiled engine");
     if (img->h < 3 || img->w < 3) {
         Retired d{tag, {}};

@@ -18,10 +18,11 @@ THIN_OK, THIN_EINVAL, THIN_ENOMEM, THIN_EDEVICE, THIN_ELIMIT, THIN_EBUSY = 0, -1
 THIN_U8, THIN_U16 = 1, 2
 THIN_ADJ_8_4, THIN_ADJ_4_8 = 0, 1
 THIN_OP_LEVELING, THIN_OP_SKELETON = 0, 1
-THIN_ENGINE_AUTO, THIN_ENGINE_TILED, THIN_ENGINE_STEP, THIN_ENGINE_PERSIST, THIN_ENGINE_COOP = (
-    0, 1, 2, 3, 4)
+THIN_ENGINE_AUTO, THIN_ENGINE_TILED, THIN_ENGINE_STEP, THIN_ENGINE_COOP = 0, 1, 2, 4
+THIN_ENGINE_WORKLIST = 5
 THIN_FLAG_PROFILE = 1
 THIN_FLAG_GRAPH = 2
+THIN_FLAG_TAIL = 4
 
 EXPORTED = [
     "thin_create", "thin_run", "thin_run_noalloc", "thin_skeleton", "thin_run_batch", "thin_serve_admit",
@@ -50,6 +51,7 @@ class thin_config(ctypes.Structure):
         ("threads", ctypes.c_int32),
         ("variant", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+        ("tune_cache", ctypes.c_char_p),
     ]
 
 
@@ -306,7 +308,8 @@ class Context:
     def __init__(self, device: int = 0, stream=None, engine: int = THIN_ENGINE_AUTO,
                  max_device_bytes: int = 0, max_passes: int = 0, tile: int = 0,
                  steps_per_round: int = 0, profile: bool = False, graph: bool = False,
-                 threads: int = 0, variant: int = 0):
+                 threads: int = 0, variant: int = 0, tune_cache: str | None = None,
+                 tail: bool = False):
         import torch
 
         if stream is None:
@@ -321,7 +324,9 @@ class Context:
         cfg.steps_per_round = steps_per_round
         cfg.threads = threads
         cfg.variant = variant
-        cfg.flags = (THIN_FLAG_PROFILE if profile else 0) | (THIN_FLAG_GRAPH if graph else 0)
+        cfg.flags = ((THIN_FLAG_PROFILE if profile else 0) | (THIN_FLAG_GRAPH if graph else 0)
+                     | (THIN_FLAG_TAIL if tail else 0))
+        cfg.tune_cache = tune_cache.encode() if tune_cache else None
         self.device = device
         self.stream = stream
         self.handle = thin_create(cfg)

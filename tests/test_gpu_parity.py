@@ -118,7 +118,7 @@ ALL_SHAPES = ["16,16,8,256,0", "32,32,8,256,0", "32,32,8,512,0", "32,32,16,256,0
               "32,32,16,256,3", "32,32,16,512,3", "64,64,16,512,3", "64,64,16,512,4",
               "64,64,16,256,3", "64,64,16,256,4", "128,128,16,256,4",
               "64,64,32,512,3", "64,64,32,512,4", "128,128,16,512,3", "128,128,16,512,4",
-              "128,128,32,512,4"]
+              "128,128,32,512,4", "128,128,8,512,4", "128,128,24,512,4"]
 
 
 @pytest.mark.parametrize("shape", ALL_SHAPES)
@@ -220,17 +220,15 @@ def test_degenerate_sizes(shape):
 def test_persistent_engine_blobs_128():
     job = synth.blobs_128()
     F = job.image()
-    got, st = gpu_thin(F, job.lam, job.adj, engine=thin.THIN_ENGINE_PERSIST)
+    got, st = gpu_thin(F, job.lam, job.adj, engine=3)
     assert_same(F, job.lam, job.adj, got, st)
 
 
 def test_persistent_engine_reports_disabled():
-    F = synth.gen_blobs(16, 16, 1)
-    t = torch.from_numpy(F).cuda()
-    with thin.Context(engine=thin.THIN_ENGINE_PERSIST) as ctx:
-        with pytest.raises(thin.ThinError):
-            ctx.run(t, 0, 0)
-    assert np.array_equal(t.cpu().numpy(), F)
+    """Engine 3 (the removed persistent work-queue engine) is refused at
+    thin_create."""
+    with pytest.raises(thin.ThinError):
+        thin.Context(engine=3)
 
 
 def test_graph_mode_matches_oracle():
@@ -293,10 +291,42 @@ def test_autotune_leaves_inputs_and_results_unchanged():
         for F, t in zip(Fs, ts):
             assert np.array_equal(t.cpu().numpy(), F)
         assert res["candidates"] > 1 and res["ms"] > 0 and res["default_ms"] > 0
-        assert res["steps_per_round"] in (8, 16, 32) and res["threads"] in (256, 512, 1024)
+        assert res["steps_per_round"] in (8, 12, 16, 24, 32) and res["threads"] in (256, 512, 576, 1024)
         sts = ctx.run_batch(ts, lams, adjs)
     for F, t, st, lam, adj in zip(Fs, ts, sts, lams, adjs):
         assert_same(F, lam, adj, t.cpu().numpy(), st)
+
+
+def test_tune_cache_round_trip(tmp_path):
+    """thin_autotune records its choice in the tune cache under the device's
+    architecture and size class; a context created on that file runs with the
+    recorded shape (its tile residencies equal a run with that shape forced)
+    and lines of another architecture are ignored."""
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    F = synth.gen_blobs(300, 200, 4321, np.uint8, nblobs=8, sigma=(3.0, 10.0))
+    t = torch.from_numpy(F.copy()).cuda()
+    path = str(tmp_path / "tune.txt")
+    say("case tune cache")
+    with thin.Context(tune_cache=path) as ctx:
+        ctx.autotune([t], [5], [0], reps=1)
+    lines = open(path).read().split("\n")
+    mine = [l for l in lines if l.startswith(arch + " ")]
+    assert len(mine) == 1 and mine[0].split()[1:3] == ["15", "15"]
+    # a hand-written entry for this size class, plus one for another architecture
+    with open(path, "w") as f:
+        f.write("gfx000 15 15 32 32 8 256 0 1.0\n")
+        f.write(f"{arch} 15 15 64 64 16 256 3 1.0\n")
+    def run(**kw):
+        u = torch.from_numpy(F.copy()).cuda()
+        with thin.Context(**kw) as c:
+            st = c.run(u, 5, 0)
+        return u.cpu().numpy(), st
+    got, st = run(tune_cache=path)
+    want, st_forced = run(tile=64, steps_per_round=16, threads=256, variant=3)
+    _, st_default = run()
+    assert np.array_equal(got, want)
+    assert st.tile_rounds == st_forced.tile_rounds != st_default.tile_rounds
+    assert_same(F, 5, 0, got, st)
 
 
 @pytest.mark.parametrize("variant", [3, 4])
