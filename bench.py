@@ -1,31 +1,36 @@
 #!/usr/bin/env python3
 """Throughput of the lambda-leveling loop on one MI355X.
 
-Default workload (one JSON line): a single 512x512 u8 ridge image (Gaussian-
-filtered noise with 20 bright 1-pixel polylines), lambda = 20, (8,4), thinned
-to stability by the plain per-image path.  A "step" is one full run of the
-loop on one image: every parity step until a pass without lowering.  Inputs
-are staged in HBM before the timed region (one copy per step, because the
-library works in place); the timed region brackets exactly --steps runs with
-a device synchronisation on both sides.
+Default workload (one JSON line): 512 uneven u8 blob images (sides log-uniform
+in 64..2048, lambda from {0, 5, 20, 50}, (8,4), 162.4 Mpixel) thinned to
+stability by one batched call.  A "step" is one `thin_run_batch` of the whole
+batch: every parity step of every image until a pass without lowering.
+Inputs are staged in HBM before the timed region (one copy per step, because
+the library works in place); the timed region brackets exactly --steps calls
+with a device synchronisation on both sides.  The same images then run
+through one plain call each, and every image of both legs is checked against
+the oracle's stored digests.
 
-Other workloads (--workload): blobs_128, blobs_8192_u16, skeleton_512 (the
-ridge image under the lambda-skeleton, lambda = 10), gradient_skeleton_512
-(a 512x512 blob image's Deriche gradient, then its lambda-skeleton, both on
-the GPU in every step), batch_512 (512
-uneven images in one batched call, compared with 512 plain calls), serving
-(Poisson arrivals at 2000 images/s of u8/u16 images with sides 64..4096
+Other workloads (--workload): ridges_512 (one 512x512 u8 ridge image,
+lambda = 20, through the plain path), blobs_128, blobs_8192_u16, skeleton_512
+(the ridge image under the lambda-skeleton, lambda = 10),
+gradient_skeleton_512 (a 512x512 blob image's Deriche gradient, then its
+lambda-skeleton, both on the GPU in every step), serving (Poisson arrivals at
+2000 images/s of u8/u16 images with sides 64..4096 from pinned host memory
 through the continuous-batching calls: throughput with p50/p99 latency from
-arrival to result, and the capacity with every request present at once).
+arrival to the result in host memory, and the capacity with every request
+present at once).
 
 The JSON line carries:
   value      Mpixel/s (pixels of input images thinned to stability per second)
-  roofline   streaming-equivalent HBM rate of the round kernel: the algorithmic
-             bytes 2*b*H*W*P of a run (b bytes per pixel, P passes) divided by
-             the summed duration of its round-kernel launches (HIP events on
-             the library's stream), against 8 TB/s
-  cpu_baseline  the CPU oracle (single-thread C, dirty-pixel sweep) on the
-             same image(s), as a reported baseline
+  roofline   the round kernel against the 32-bit integer vector peak (it is
+             VALU-bound): 40 integer operations per pixel-pass (H*W*P) per
+             launch over the average launch duration (HIP events on the
+             library's stream, in a second pass over the same work); the HBM
+             figure (2*b bytes per pixel-pass against 8 TB/s) and the fraction
+             counting only the oracle's examinations ride beside it
+  cpu_baseline  the CPU oracle (dirty-pixel sweep) on a sample of the same
+             images, as a reported baseline
 """
 from __future__ import annotations
 
@@ -48,6 +53,39 @@ ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # destructible), the lambda test (1 subtraction, 8 compares, 4 for the
 # component count), alpha- (8 selects, 7 maxima), 3 to select and write
 OPS_PER_EXAMINATION = 40
+
+
+def _roofline(px_passes, alg_bytes, launches, kernel_ms, traffic, x_method, timing, steps=1):
+    """The round kernel's roofline: ALU-bound in streaming-equivalent units
+    (OPS_PER_EXAMINATION integer ops per pixel-pass), the HBM figure and the
+    method-work fraction (the oracle's examinations only) beside it."""
+    launches = max(int(launches), 1)
+    avg_s = kernel_ms / 1e3 / launches
+    ok = kernel_ms > 0
+    ops_launch = OPS_PER_EXAMINATION * px_passes / launches
+    tops = ops_launch / avg_s / 1e12 if ok else None
+    gbs = alg_bytes / launches / avg_s / 1e9 if ok else None
+    method = OPS_PER_EXAMINATION * x_method / (kernel_ms / 1e3) / 1e12 if ok else None
+    return {
+        "bound": "alu", "kernel": "k_round",
+        "achieved": round(tops, 3) if tops else None,
+        "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s",
+        "frac": round(tops / ALU_PEAK_TOPS, 4) if tops else None,
+        "traffic": traffic,
+        "launches_per_step": round(launches / steps, 2),
+        "avg_launch_us": round(avg_s * 1e6, 3),
+        "alg_ops_per_launch": round(ops_launch, 1),
+        "ops_per_pixel_pass": OPS_PER_EXAMINATION,
+        "hbm": {"achieved": round(gbs, 2) if gbs else None, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4) if gbs else None,
+                "alg_bytes_per_launch": round(alg_bytes / launches, 1),
+                "traffic_GBps": (round(traffic / avg_s / 1e9, 2) if traffic and ok else None)},
+        "method_work_frac": round(method / ALU_PEAK_TOPS, 4) if method else None,
+        "timing": timing,
+        "units": "streaming-equivalent: one characterisation (40 integer ops) and one read "
+                 "and write of the pixel per pixel-pass (H*W*P); method_work_frac counts "
+                 "the oracle's examinations X instead",
+    }
 
 
 def _percentile(xs, q):
@@ -185,8 +223,6 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, graph=False
     elapsed = t1 - t0
     mpx = h * w * steps / elapsed / 1e6
     alg_bytes = 2 * b * h * w * ref.passes * steps
-    kernel_s = kernel_ms / 1e3
-    achieved = alg_bytes / kernel_s / 1e9 if kernel_s > 0 else None
     traffic = _traffic_for("k_round", name)
     out = {
         "metric": METRIC,
@@ -207,29 +243,18 @@ def bench_single(job, name, steps, warmup, cpu_s, tile, k, engine=0, graph=False
                                  if front else None),
                    "images_per_step": 1,
                    "path": "plain (thin_run)", "graph": graph,
-                   "engine": {0: "auto", 1: "tiled", 2: "step", 3: "persistent",
-                              4: "cooperative"}[engine]},
+                   "engine": {0: "auto", 1: "tiled", 2: "step", 4: "cooperative",
+                              5: "worklist"}[engine]},
         "images_per_s": round(steps / elapsed, 2),
         "latency_ms_p50": round(_percentile(lat, 0.5), 4),
         "latency_ms_p99": round(_percentile(lat, 0.99), 4),
         "passes": int(stats.passes),
         "lowerings": int(stats.lowerings),
         "bit_exact": bit_exact,
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_round",
-            "achieved": round(achieved, 2) if achieved else None,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-            "traffic": traffic,
-            "traffic_GBps": (round(traffic / (kernel_ms * 1e-3 / launches) / 1e9, 2)
-                             if traffic else None),
-            "launches_per_step": round(launches / steps, 2),
-            "avg_launch_us": round(kernel_ms * 1e3 / launches, 3),
-            "alg_bytes_per_launch": round(alg_bytes / launches, 1),
-            "timing": "kernel durations from HIP events in a second pass over the same runs",
-        },
+        "roofline": _roofline(h * w * ref.passes * steps, alg_bytes, launches, kernel_ms,
+                              traffic, ref.examinations * steps,
+                              "kernel durations from HIP events in a second pass over the "
+                              "same runs", steps),
         # the method's own work (oracle dirty-pixel sweep): examinations X
         # against the streaming H*W*P pixel-passes
         "method_work": {"examinations": int(ref.examinations), "pixel_passes": h * w * ref.passes,
@@ -428,15 +453,6 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, tune=True, graph=False,
     alg_one = sum(2 * F.size * st.passes for F, st in zip(Fs, stats))
     x_method = sum(g["examinations"] for g in golden)
     px_passes = sum(F.size * st.passes for F, st in zip(Fs, stats))
-    avg_launch_s = kernel_ms / 1e3 / max(launches, 1)
-    achieved = alg_one / max(launches, 1) / avg_launch_s / 1e9 if kernel_ms > 0 else None
-    # the ALU roofline in the same streaming-equivalent units (one
-    # characterisation per pixel-pass), and in the method's own work (the
-    # oracle's examinations X)
-    ops_launch = OPS_PER_EXAMINATION * px_passes / max(launches, 1)
-    achieved_tops = ops_launch / avg_launch_s / 1e12 if kernel_ms > 0 else None
-    method_tops = (OPS_PER_EXAMINATION * x_method / (kernel_ms / 1e3) / 1e12
-                   if kernel_ms > 0 else None)
     traffic = _traffic_for("k_round", "batch_512")
     out = {
         "metric": METRIC,
@@ -465,26 +481,9 @@ def bench_batch(steps, warmup, cpu_s, tile, k, engine=0, tune=True, graph=False,
         "bit_exact_plain": plain_exact,
         "bit_exact_images": sum(same_input),
         "streaming_equiv_frac_of_hbm": round(alg_one * steps / elapsed / 1e9 / HBM_PEAK_GBS, 4),
-        "roofline": {
-            "bound": "alu", "kernel": "k_round",
-            "achieved": round(achieved_tops, 3) if achieved_tops else None,
-            "peak": round(ALU_PEAK_TOPS, 2), "unit": "Tops/s",
-            "frac": round(achieved_tops / ALU_PEAK_TOPS, 4) if achieved_tops else None,
-            "traffic": traffic,
-            "launches_per_step": launches,
-            "avg_launch_us": round(avg_launch_s * 1e6, 3),
-            "alg_ops_per_launch": round(ops_launch, 1),
-            "ops_per_pixel_pass": OPS_PER_EXAMINATION,
-            "hbm": {"achieved": round(achieved, 2) if achieved else None, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-                    "alg_bytes_per_launch": round(alg_one / max(launches, 1), 1)},
-            "method_work_frac": round(method_tops / ALU_PEAK_TOPS, 4) if method_tops else None,
-            "timing": "HIP events around every round launch on the library's stream, in a "
-                      "second pass over the same batch",
-            "units": "streaming-equivalent: one characterisation (40 integer ops) and one read "
-                     "and write of the pixel per pixel-pass (H*W*P); method_work_frac counts "
-                     "the oracle's examinations X instead",
-        },
+        "roofline": _roofline(px_passes, alg_one, launches, kernel_ms, traffic, x_method,
+                              "HIP events around every round launch on the library's "
+                              "stream, in a second pass over the same batch"),
         # the method's own work (oracle dirty-pixel sweep, stored per image)
         # against the streaming H*W*P pixel-passes and the kernels' own count
         "method_work": {"examinations": x_method, "pixel_passes": px_passes,
@@ -572,8 +571,8 @@ def bench_serving(cpu_s, tile, k, seconds=1.0, rate=2000.0, rounds_per_step=2,
         exact &= (st.passes, st.lowerings) == (ref.passes, ref.lowerings)
     alg = sum(2 * (1 if j.dtype == synth.U8 else 2) * j.h * j.w * cap.stats[i].passes
               for i, j in enumerate(jobs))
-    kernel_s = prof.kernel_ms / 1e3
-    achieved = alg / kernel_s / 1e9 if kernel_s > 0 else None
+    px_passes = sum(j.h * j.w * cap.stats[i].passes for i, j in enumerate(jobs))
+    x_gpu = sum(st.examinations for st in cap.stats.values())
     out = {
         "metric": METRIC,
         "value": round(rep.mpixel_per_s, 3),
@@ -600,16 +599,11 @@ def bench_serving(cpu_s, tile, k, seconds=1.0, rate=2000.0, rounds_per_step=2,
         "bit_exact_sample": exact,
         "bit_exact_sample_requests": [{"h": jobs[i].h, "w": jobs[i].w,
                                        "dtype": np.dtype(jobs[i].dtype).name} for i in sample],
-        "roofline": {
-            "bound": "hbm", "kernel": "k_round",
-            "achieved": round(achieved, 2) if achieved else None,
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-            "traffic": None,
-            "launches": int(prof.launches),
-            "avg_launch_us": round(prof.kernel_ms * 1e3 / max(prof.launches, 1), 3),
-            "timing": "HIP events around every round launch of a profiled capacity pass",
-        },
+        # no stored oracle count for the trace: the method-work fraction
+        # uses the kernels' own examinations (an upper bound on X)
+        "roofline": _roofline(px_passes, alg, prof.launches, prof.kernel_ms, None, x_gpu,
+                              "HIP events around every round launch of a profiled capacity "
+                              "pass"),
     }
     if cpu_s > 0:
         smalls = [(host_in[i].numpy(), jobs[i].lam, jobs[i].adj) for i in order[:200]]
