@@ -1033,6 +1033,7 @@ struct BTile {
     static_assert(TH % 4 == 0 && TW % 4 == 0, "tile sides must be multiples of 4");
     static_assert(NT % 64 == 0 && CLASS_WORDS <= NT, "one bitmap word per thread");
     static_assert(WAVE_WORDS <= 64, "one bitmap word per lane");
+    static_assert(LWW + 1 <= 8, "reads one row and word past the lowered bitmaps stay in the ring");
     static_assert(LAT_H <= 256 && LAT_W <= 256, "list entries hold a row and a column byte");
     static_assert(!SEED || TW % 32 == 0, "history bitmaps need a tile width multiple of 32");
     static_assert(!SEED || 2 * K <= TH, "history seeding needs the region inside the 3x3 tile block");
@@ -1151,37 +1152,88 @@ struct BTile {
 
         const uint32_t lambda = d.lambda;
         const int wave = tid >> 6, lane = tid & 63;
-        const int myw = lane < WAVE_WORDS ? wave * WAVE_WORDS + lane : CLASS_WORDS;  // its word
+        // The bitmap word this lane owns; lanes without one read a valid word
+        // (the last) and take nothing.  Every read below is unconditional, so
+        // a step's reads go out together: a word of a neighbouring row or
+        // column outside the lattice reads some other word of the flag area
+        // (they all lie inside it) and is masked to zero.
+        const bool has_word = lane < WAVE_WORDS && wave * WAVE_WORDS + lane < CLASS_WORDS;
+        const int myw = has_word ? wave * WAVE_WORDS + lane : CLASS_WORDS - 1;
         const int wa = myw / LWW, wj = myw - (myw / LWW) * LWW;
+        const bool up_ok = wa > 0, dn_ok = wa + 1 < LAT_H, lt_ok = wj > 0, rt_ok = wj + 1 < LWW;
+        const uint32_t* own_dl = s_dl + myw;  // word (wa, wj) of class 0's lowered bitmap
         int my_count = 0, my_last = -1;  // interior lowerings, last step with one
         int my_exams = 0;                // candidates characterised (thread 0 counts the lists)
-        for (int tau = 0; tau < nsteps; ++tau) {
-            const int c = tau & 3, si = c >> 1, sj = c & 1;
-            // A step's candidates come from the residency's seeds (first 4
-            // steps) and from pixels lowered during the 4 steps before it.
-            // When neither exists the step cannot lower anything; once 4
-            // steps in a row are quiet and the seeds are used up, no later
-            // step of the residency can either.  The flags were written
-            // before the last barrier, so every thread takes the same
-            // branch.  A skipped step still clears the two ring slots it
-            // owns (its "lowered" flag, and the list length of step tau + 4,
-            // whose last readers were at step tau - 4).
+        bool done = false;               // block-uniform: no later step can lower anything
+
+        // One step of class C = tau mod 4.  A step's candidates come from the
+        // residency's seeds (first 4 steps) and from pixels lowered during the
+        // 4 steps before it.  When neither exists the step cannot lower
+        // anything; once 4 steps in a row are quiet and the seeds are used up,
+        // no later step of the residency can either.  The flags were written
+        // before the last barrier, so every thread takes the same branch.  A
+        // skipped step still clears the two ring slots it owns (its "lowered"
+        // flag, and the list length of step tau + 4, whose last readers were
+        // at step tau - 4).
+        auto step = [&](auto cls, int tau) __attribute__((always_inline)) {
+            constexpr int c = decltype(cls)::value, si = c >> 1, sj = c & 1;
+            const uint64_t lw = *reinterpret_cast<const uint64_t*>(s_low);
+            const bool seeds_c = s_seeds[c] != 0;
+            // Candidates of this word: still pending from the residency's
+            // start, lowered themselves 4 steps ago, or next to a pixel
+            // lowered during the last 3 steps (the lowered bitmap of each
+            // other class, spread over the cells whose 3x3 holds it: rows a
+            // or a+-1 and columns b or b+-1 by parity).  Read before the quiet
+            // test; in a quiet step every one of these words is zero.
+            uint32_t want = s_db[c * CLASS_WORDS + myw] | own_dl[c * CLASS_WORDS];
+#pragma unroll
+            for (int k = 1; k < 4; ++k) {
+                const int o = (c + k) & 3, oi = o >> 1, oj = o & 1;
+                const uint32_t* bm = own_dl + o * CLASS_WORDS;  // word (wa, wj) of class o
+                // rows of o next to row wa of c: wa itself when oi == si, else
+                // wa - 1 and wa (oi > si) or wa and wa + 1 (oi < si)
+                const int dr = oi > si ? -LWW : LWW;
+                const bool r_ok = oi > si ? up_ok : dn_ok;
+                uint32_t w0 = bm[0], prev = 0u, next = 0u;
+                if (oj > sj) prev = bm[-1];
+                if (oj < sj) next = bm[1];
+                if (oi != si) {
+                    const uint32_t x0 = bm[dr];
+                    const uint32_t xp = oj > sj ? bm[dr - 1] : 0u;
+                    const uint32_t xn = oj < sj ? bm[dr + 1] : 0u;
+                    w0 |= r_ok ? x0 : 0u;
+                    prev |= r_ok ? xp : 0u;
+                    next |= r_ok ? xn : 0u;
+                }
+                if (oj == sj) {
+                    want |= w0;
+                } else if (oj > sj) {  // cells b - 1 and b
+                    want |= w0 | (w0 << 1) | ((lt_ok ? prev : 0u) >> 31);
+                } else {               // cells b and b + 1
+                    want |= w0 | (w0 >> 1) | ((rt_ok ? next : 0u) << 31);
+                }
+            }
             {
-                const uint64_t lw = *reinterpret_cast<const uint64_t*>(s_low);
                 const int sh = 8 * ((tau + 4) & 7);  // slots tau-4 .. tau-1, in ring order
                 const uint64_t rot = sh ? ((lw >> sh) | (lw << (64 - sh))) : lw;
                 const uint64_t recent = rot & 0xFFFFFFFFull;
-                const bool quiet = recent == 0ull && !(tau < 4 && s_seeds[c]);
-                if (quiet) {
-                    if (tau >= 4) break;
+                if (recent == 0ull && !(tau < 4 && seeds_c)) {
+                    if (tau >= 4) {
+                        done = true;
+                        return;
+                    }
                     if (tid == 0) {
                         s_low[tau & 7] = 0;
                         s_total[(tau + 4) & 7] = 0;
                     }
-                    continue;
+                    return;
                 }
             }
             if (tid == 0) s_low[tau & 7] = 0;
+            if (has_word) {
+                s_db[c * CLASS_WORDS + myw] = 0u;
+                s_dl[c * CLASS_WORDS + myw] = 0u;
+            }
             // Exact region after tau steps, clipped to the image interior,
             // as lattice rows a (region row 2a + si) and columns b (2b + sj).
             const int r_lo = max(tau + 1, 1 - ry0), r_hi = min(RH - 2 - tau, d.h - 2 - ry0);
@@ -1189,40 +1241,9 @@ struct BTile {
             const int a_lo = (r_lo - si + 1) >> 1, a_hi = (r_hi - si) >> 1;
             const int b_lo = (c_lo - sj + 1) >> 1, b_hi = (c_hi - sj) >> 1;
             uint32_t take = 0u;
-            if (myw < CLASS_WORDS) {
-                // Candidates of this word to examine: still pending from the
-                // residency's start, lowered themselves 4 steps ago, or next to
-                // a pixel lowered during the last 3 steps (the lowered bitmap
-                // of each other class, spread over the cells whose 3x3 holds
-                // it: rows a or a+-1 and columns b or b+-1 by parity).
-                uint32_t want = s_db[c * CLASS_WORDS + myw] | s_dl[c * CLASS_WORDS + myw];
-                s_db[c * CLASS_WORDS + myw] = 0u;
-                s_dl[c * CLASS_WORDS + myw] = 0u;
-#pragma unroll
-                for (int k = 1; k < 4; ++k) {
-                    const int o = (c + k) & 3, oi = o >> 1, oj = o & 1;
-                    const uint32_t* lo_bm = s_dl + o * CLASS_WORDS;
-                    const int r0 = oi == si ? wa : (oi > si ? wa - 1 : wa);
-                    const int nr = oi == si ? 1 : 2;
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const int row = r0 + q;
-                        if (q >= nr || row < 0 || row >= LAT_H) continue;
-                        const uint32_t* rw = lo_bm + row * LWW;
-                        const uint32_t w = rw[wj];
-                        if (oj == sj) {
-                            want |= w;
-                        } else if (oj > sj) {  // cells b - 1 and b
-                            const uint32_t prev = wj > 0 ? rw[wj - 1] : 0u;
-                            want |= w | (w << 1) | (prev >> 31);
-                        } else {               // cells b and b + 1
-                            const uint32_t next = wj + 1 < LWW ? rw[wj + 1] : 0u;
-                            want |= w | (w >> 1) | (next << 31);
-                        }
-                    }
-                }
+            {
                 const int lo = max(b_lo - 32 * wj, 0), hi = min(b_hi - 32 * wj, 31);
-                if (wa >= a_lo && wa <= a_hi && lo <= hi) {
+                if (has_word && wa >= a_lo && wa <= a_hi && lo <= hi) {
                     const uint32_t mask = (hi == 31 ? ~0u : ((2u << hi) - 1u)) & ~((1u << lo) - 1u);
                     take = want & mask;
                 }
@@ -1281,6 +1302,16 @@ struct BTile {
             if (__ballot(lowered) != 0ull && lane == 0) s_low[tau & 7] = 1;
             if (inner) my_last = tau;
             __syncthreads();
+        };
+        using C0 = std::integral_constant<int, 0>;
+        using C1 = std::integral_constant<int, 1>;
+        using C2 = std::integral_constant<int, 2>;
+        using C3 = std::integral_constant<int, 3>;
+        for (int tau = 0; tau < nsteps && !done; tau += 4) {
+            step(C0{}, tau);
+            if (tau + 1 < nsteps && !done) step(C1{}, tau + 1);
+            if (tau + 2 < nsteps && !done) step(C2{}, tau + 2);
+            if (tau + 3 < nsteps && !done) step(C3{}, tau + 3);
         }
 
         store(d, gy0, gx0, src, dst, s_img, tid);
