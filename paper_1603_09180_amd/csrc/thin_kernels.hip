@@ -569,8 +569,10 @@ __device__ __forceinline__ uint32_t history_word_t(const Seed* sd, int gi, int a
     const int tcol = a / WPR, trow = gi / TH;
     if (tcol >= sd->tiles_x || trow >= sd->tiles_y) return 0u;
     const int n = sd->tile0 + trow * sd->tiles_x + tcol;
-    if (sd->prev_round[n] != sd->r - 1) return 0u;
-    return sd->prev_bits[((int64_t)n * TH + (gi - trow * TH)) * WPR + (a - tcol * WPR)];
+    // both reads go out together: the bitmap of any tile of the grid may be
+    // read, and is discarded unless the tile wrote it in round r - 1
+    const uint32_t bits = sd->prev_bits[((int64_t)n * TH + (gi - trow * TH)) * WPR + (a - tcol * WPR)];
+    return sd->prev_round[n] == sd->r - 1 ? bits : 0u;
 }
 
 // Geometry of a tile residency: a TH x TW interior plus a K-pixel halo,
@@ -598,6 +600,13 @@ struct Tile {
 
 
     // Tile and halo from src into s_img (no barrier).
+    // Work a residency can start before the block knows whether the tile
+    // runs (none for this type).
+    static __device__ __forceinline__ void prefetch(const View&, int, int, const Seed*, uint8_t*,
+                                                    uint32_t*, int)
+    {
+    }
+
     static __device__ __forceinline__ void stage(const View& d, int gy0, int gx0, const void* src,
                                                  const void* dst, uint16_t* s_img, int tid)
     {
@@ -811,6 +820,13 @@ struct RTile {
 
     // Tile and halo from src into s_img, spare rows and columns zeroed (they
     // are read into windows but never used by a candidate); no barrier.
+    // Work a residency can start before the block knows whether the tile
+    // runs (none for this type).
+    static __device__ __forceinline__ void prefetch(const View&, int, int, const Seed*, uint8_t*,
+                                                    uint32_t*, int)
+    {
+    }
+
     static __device__ __forceinline__ void stage(const View& d, int gy0, int gx0, const void* src,
                                                  const void*, uint16_t* s_img, int tid)
     {
@@ -1034,10 +1050,53 @@ struct BTile {
     static_assert(NT % 64 == 0 && CLASS_WORDS <= NT, "one bitmap word per thread");
     static_assert(WAVE_WORDS <= 64, "one bitmap word per lane");
     static_assert(LWW + 1 <= 8, "reads one row and word past the lowered bitmaps stay in the ring");
+    static_assert(LIST_ELEMS >= NT, "every thread may read the first list entry");
     static_assert(LAT_H <= 256 && LAT_W <= 256, "list entries hold a row and a column byte");
     static_assert(!SEED || TW % 32 == 0, "history bitmaps need a tile width multiple of 32");
     static_assert(!SEED || 2 * K <= TH, "history seeding needs the region inside the 3x3 tile block");
 
+
+    // Everything a residency can start before the block knows whether the
+    // tile runs, so that it overlaps the staging loads instead of following
+    // them: the ring slots and flags, the cleared lowered bitmaps and, when
+    // seeded, the previous round's change map of the region in 32-pixel
+    // words (two dependent global reads per word).  None of it is read by the
+    // previous tile's tail (which reads only the change bitmap s_bits and the
+    // block counters, both set up after the decision).
+    static __device__ __forceinline__ void prefetch(const View& d, int gy0, int gx0, const Seed* sd,
+                                                    uint8_t* s_flags, uint32_t* s_cw, int tid)
+    {
+        uint32_t* s_dl = reinterpret_cast<uint32_t*>(s_flags) + 4 * CLASS_WORDS;
+        int* s_total = reinterpret_cast<int*>(s_dl + 4 * CLASS_WORDS);
+        uint8_t* s_low = reinterpret_cast<uint8_t*>(s_total + 8);
+        uint8_t* s_seeds = s_low + 8;
+        const bool seeded = SEED && sd != nullptr && sd->r > 0;
+        for (int i = tid; i < 4 * CLASS_WORDS; i += NT) s_dl[i] = 0u;
+        if (tid < 8) {
+            s_total[tid] = 0;
+            s_low[tid] = 0;
+            s_seeds[tid] = seeded ? 0 : 1;
+        }
+        if constexpr (SEED) {
+            if (seeded) {
+                const int ry0 = gy0 - K, rx0 = gx0 - K;
+                for (int it = tid; it < RH * RWW; it += NT) {
+                    const int y = it / RWW, j = it - y * RWW;
+                    const int gi = ry0 + y;
+                    uint32_t word = 0u;
+                    if (gi >= 0 && gi < d.h) {
+                        const int c0 = rx0 + 32 * j;
+                        const int a = (c0 >= 0) ? (c0 >> 5) : -((31 - c0) >> 5);
+                        const int sh = c0 - 32 * a;
+                        const uint32_t lo = history_word_t<TH, TW>(sd, gi, a);
+                        const uint32_t hi = history_word_t<TH, TW>(sd, gi, a + 1);
+                        word = sh ? ((lo >> sh) | (hi << (32 - sh))) : lo;
+                    }
+                    s_cw[it] = word;
+                }
+            }
+        }
+    }
 
     static __device__ __forceinline__ void stage(const View& d, int gy0, int gx0, const void* src,
                                                  const void* dst, E* s_img, int tid)
@@ -1092,32 +1151,8 @@ struct BTile {
         }
         if constexpr (SEED)
             for (int i = tid; i < TH * WPR; i += NT) s_bits[i] = 0u;
-        for (int i = tid; i < 4 * CLASS_WORDS; i += NT) s_dl[i] = 0u;
-        if (tid < 8) {
-            s_total[tid] = 0;
-            s_low[tid] = 0;
-            s_seeds[tid] = seeded ? 0 : 1;
-        }
-        if (!seeded) {
+        if (!seeded)
             for (int i = tid; i < 4 * CLASS_WORDS; i += NT) s_db[i] = valid_bits(i % LWW);
-        } else if constexpr (SEED) {
-            // Changed map of the region in 32-pixel words, as in Tile.
-            for (int it = tid; it < RH * RWW; it += NT) {
-                const int y = it / RWW, j = it - y * RWW;
-                const int gi = ry0 + y;
-                uint32_t word = 0u;
-                if (gi >= 0 && gi < d.h) {
-                    const int c0 = rx0 + 32 * j;
-                    const int a = (c0 >= 0) ? (c0 >> 5) : -((31 - c0) >> 5);
-                    const int sh = c0 - 32 * a;
-                    const uint32_t lo = history_word_t<TH, TW>(sd, gi, a);
-                    const uint32_t hi = history_word_t<TH, TW>(sd, gi, a + 1);
-                    word = sh ? ((lo >> sh) | (hi << (32 - sh))) : lo;
-                }
-                s_cw[it] = word;
-            }
-        }
-        __syncthreads();
         if constexpr (SEED) if (seeded) {
             // Flag word j of class (si, sj) at lattice row a covers region
             // row 2a + si, columns 64j + sj + 2t (t < 32): the 3x3-dilated
@@ -1126,29 +1161,34 @@ struct BTile {
                 const int c = i / CLASS_WORDS, rem = i - c * CLASS_WORDS;
                 const int a = rem / LWW, j = rem - a * LWW;
                 const int y = 2 * a + (c >> 1), sj = c & 1;
+                // every read is unconditional (clamped into the map, the
+                // value masked), so all of them go out together
                 uint32_t half[2];
 #pragma unroll
                 for (int hw = 0; hw < 2; ++hw) {
                     const int w = 2 * j + hw;
+                    const int wc = w < RWW ? w : RWW - 1;
+                    const int wl = wc > 0 ? wc - 1 : 0, wr = wc + 1 < RWW ? wc + 1 : wc;
                     uint32_t m = 0u;
-                    if (w < RWW) {
-                        for (int dy = -1; dy <= 1; ++dy) {
-                            const int yy = y + dy;
-                            if (yy < 0 || yy >= RH) continue;
-                            const uint32_t cc = s_cw[yy * RWW + w];
-                            const uint32_t l = w > 0 ? s_cw[yy * RWW + w - 1] : 0u;
-                            const uint32_t r = w + 1 < RWW ? s_cw[yy * RWW + w + 1] : 0u;
-                            m |= cc | (cc << 1) | (cc >> 1) | (l >> 31) | (r << 31);
-                        }
+#pragma unroll
+                    for (int dy = -1; dy <= 1; ++dy) {
+                        const int yy = y + dy;
+                        const int yc = yy < 0 ? 0 : (yy >= RH ? RH - 1 : yy);
+                        const uint32_t cc = s_cw[yc * RWW + wc];
+                        const uint32_t l = s_cw[yc * RWW + wl];
+                        const uint32_t r = s_cw[yc * RWW + wr];
+                        const uint32_t row = cc | (cc << 1) | (cc >> 1) | (wc > 0 ? l >> 31 : 0u) |
+                                             (wc + 1 < RWW ? r << 31 : 0u);
+                        m |= (yy >= 0 && yy < RH) ? row : 0u;
                     }
-                    half[hw] = even_bits(m >> sj);
+                    half[hw] = w < RWW ? even_bits(m >> sj) : 0u;
                 }
                 const uint32_t word = (half[0] | (half[1] << 16)) & valid_bits(j);
                 s_db[i] = word;
                 if (word) s_seeds[c] = 1;
             }
-            __syncthreads();
         }
+        __syncthreads();
 
         const uint32_t lambda = d.lambda;
         const int wave = tid >> 6, lane = tid & 63;
@@ -1267,14 +1307,18 @@ struct BTile {
                 }
             }
             __syncthreads();
+            // the first entry is read with the length (it is in the list
+            // whenever tid < total)
             const int total = s_total[tau & 7];
+            int next_cell = s_list[tid];
             if (tid == 0) {
                 s_total[(tau + 4) & 7] = 0;
                 my_exams += total;
             }
             bool inner = false, lowered = false;
             for (int i = tid; i < total; i += NT) {
-                const int cell = s_list[i];
+                const int cell = next_cell;
+                if (i + NT < total) next_cell = s_list[i + NT];
                 const int a = cell >> 8, b = cell & 0xFF;
                 const int lr = 2 * a + si, lc = 2 * b + sj;
                 E* p = s_img + lr * RWP + lc;
@@ -1406,9 +1450,10 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
     // in which g itself lowered something.  Neighbours of this round may raise
     // tile_state[2g] to r + 1 while it is read here (only adding work), so one
     // thread decides and the barrier broadcasts a block-uniform answer.  The
-    // tile is staged before the answer is known, so its loads overlap the
-    // state read; the barrier also completes the staging and orders it after
-    // the previous tile's readers of LDS.
+    // tile is staged (and the residency's set-up started) before the answer
+    // is known, so its loads overlap the state read; the barrier also
+    // completes the staging and orders it after the previous tile's readers
+    // of LDS.
     int act = 0, chg = 0;
     if (tid == 0) {
         act = __hip_atomic_load(&st[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1425,18 +1470,6 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
         lut_adj = d->adj;
         for (int i = tid; i < 256; i += NT) s_lut[i] = lut_g[lut_adj * 256 + i];
     }
-    T::stage(v, gy0, gx0, src, dst, s_img, tid);
-    const int vote = tid == 0 ? ((r == 0 || act >= r) ? 1 : (chg == r - 1 ? 2 : 0)) : 0;
-    const int decision = __syncthreads_or(vote == 1) ? 1 : (__syncthreads_or(vote == 2) ? 2 : 0);
-    if (decision != 1) {
-        // Stable for this round.  The output buffer already equals the input
-        // unless the tile changed during the previous round.
-        if (decision == 2) {
-            T::store(v, gy0, gx0, src, dst, s_img, tid);
-            __syncthreads();  // the next tile's staging overwrites s_img
-        }
-        return 0;
-    }
     Seed sd{};
     const int64_t words = var_seeded(VAR) ? (int64_t)ntiles * TH * T::WPR : 0;
     sd.prev_bits = hist_bits + ((r + 1) & 1) * words;
@@ -1450,6 +1483,19 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
     sd.ty = ty;
     sd.tx = tx;
     sd.g = g;
+    T::stage(v, gy0, gx0, src, dst, s_img, tid);
+    T::prefetch(v, gy0, gx0, var_seeded(VAR) ? &sd : nullptr, s_dirty, s_cw, tid);
+    const int vote = tid == 0 ? ((r == 0 || act >= r) ? 1 : (chg == r - 1 ? 2 : 0)) : 0;
+    const int decision = __syncthreads_or(vote == 1) ? 1 : (__syncthreads_or(vote == 2) ? 2 : 0);
+    if (decision != 1) {
+        // Stable for this round.  The output buffer already equals the input
+        // unless the tile changed during the previous round.
+        if (decision == 2) {
+            T::store(v, gy0, gx0, src, dst, s_img, tid);
+            __syncthreads();  // the next tile's staging overwrites s_img
+        }
+        return 0;
+    }
     int last_tau;
     const int count = T::run(v, gy0, gx0, t0, nsteps, src, dst, s_img, s_dirty, s_bits, s_cw,
                              var_seeded(VAR) ? &sd : nullptr, s_lut, s_count, s_last, s_exam,
