@@ -46,6 +46,9 @@ struct ImgCnt {
 struct WorkList {
     int32_t* list;
     int32_t* count;
+    int32_t* grab;     // [6]: next list position to hand out in round R, one counter per
+                       // pixel-type launch of the round (grab[2 * (R % 3) + u16]),
+                       // cleared like count
     int32_t* listed;
     int32_t cap;
     int32_t full;    // the launch round that visits every tile (-1: none)

@@ -172,6 +172,7 @@ __global__ void k_init_state(ImgCnt* cnt, int nimg, int32_t* tile_last, int ntil
     if (wl.list != nullptr) {
         if (i < ntiles) wl.listed[i] = -1;
         if (i < 3) wl.count[i] = 0;
+        if (i < 6) wl.grab[i] = 0;
     }
     if (hist_round && i < 2 * ntiles) hist_round[i] = -1;
     if (i < nimg) {
@@ -1432,12 +1433,25 @@ __device__ __forceinline__ int round_tile(const ImgDev* __restrict__ imgs, ImgCn
     const int tid = threadIdx.x;
     const int ii = (kflags & kOneImage) ? 0 : tile_img[g];
     const ImgDev* d = imgs + ii;
-    if (((kflags & kOnlyU8) && d->dtype != 1) || ((kflags & kOnlyU16) && d->dtype != 2)) return 0;
+    // A tile that is not this launch's returns at once; the barrier keeps the
+    // block's tile hand-out (written by thread 0 before the tile, read by all
+    // after it) ordered as a visited tile's barriers do.  Every condition
+    // here is the same for the whole block.
+    if (((kflags & kOnlyU8) && d->dtype != 1) || ((kflags & kOnlyU16) && d->dtype != 2)) {
+        __syncthreads();
+        return 0;
+    }
     const int r = round - d->round0;
-    if (r < 0) return 0;
+    if (r < 0) {
+        __syncthreads();
+        return 0;
+    }
     const int t0 = r * K;
     const int nsteps = min(K, d->max_steps - t0);
-    if (nsteps <= 0) return 0;
+    if (nsteps <= 0) {
+        __syncthreads();
+        return 0;
+    }
     const int lt = g - d->tile0;
     const int ty = lt / d->tiles_x, tx = lt - ty * d->tiles_x;
     const int slot = d->slot;
@@ -1596,13 +1610,33 @@ void k_round(const ImgDev* __restrict__ imgs, ImgCnt* cnt,
     int lut_adj = -1;
     const bool all = wl.list == nullptr || round == wl.full;
     const int n = all ? ntiles : wl.count[round % 3];
-    if (wl.list != nullptr && blockIdx.x == 0 && threadIdx.x == 0) wl.count[(round + 2) % 3] = 0;
+    if (wl.list != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+        wl.count[(round + 2) % 3] = 0;
+        wl.grab[2 * ((round + 2) % 3)] = 0;
+        wl.grab[2 * ((round + 2) % 3) + 1] = 0;
+    }
     const int32_t* mine = all ? nullptr : wl.list + (round & 1) * wl.cap;
-    for (int i = blockIdx.x; i < n; i += gridDim.x)
+    // Each block takes its first tile by its index and every later one from
+    // a counter shared by the round's blocks, so blocks that drew cheap
+    // tiles take more of them (tiles differ widely in cost: partial tiles
+    // at image borders, quiet ones that are skipped).  Thread 0 claims the
+    // next position while the current tile runs; two slots, so that a slot
+    // is written again only after every thread has passed a barrier of the
+    // tile in between.  The u8 and u16 launches of one round draw from
+    // counters of their own.
+    __shared__ int s_next[2];
+    int32_t* grab = wl.list != nullptr ? wl.grab + 2 * (round % 3) + ((kflags & kOnlyU16) ? 1 : 0)
+                                       : nullptr;
+    int i = blockIdx.x;
+    for (int k = 0; i < n; ++k) {
+        if (threadIdx.x == 0)
+            s_next[k & 1] = grab ? (int)gridDim.x + atomicAdd(grab, 1) : i + (int)gridDim.x;
         round_tile<TH, TW, K, NT, VAR, E>(imgs, cnt, tile_img, tile_last, all ? i : mine[i], round,
                                           ntiles, hist_bits, hist_round, s_img, s_dirty, s_bits,
                                           s_cw, lut_g, s_lut, lut_adj, &s_count, &s_last, &s_exam,
                                           wl, kflags);
+        i = s_next[k & 1];
+    }
 }
 
 // ------------------------------------------------------------------ k_coop

@@ -508,7 +508,7 @@ struct TiledBufs {
     uint32_t* hist_bits;  // 2 * ntiles * history_words(shape)
     int32_t* hist_round;  // 2 per tile
     int32_t* wl_list;     // 2 per tile
-    int32_t* wl_meta;     // 4 + 1 per tile
+    int32_t* wl_meta;     // 12 + 1 per tile
     int32_t* small;       // 16 words
 };
 
@@ -531,7 +531,8 @@ int drive_tiled(thin_ctx* ctx, TileShape shape, const ImgDev* h_imgs, int nimg, 
     wl.full = 0;
     if (ntiles > 2 * grid) wl.list = b.wl_list;
     wl.count = b.wl_meta;
-    wl.listed = wl.count + 4;
+    wl.grab = wl.count + 4;
+    wl.listed = wl.count + 12;
     wl.cap = ntiles;
     HIP_TRY(ctx, thin::launch_init_state(ctx->stream, b.cnt, nimg, b.tile_last, ntiles,
                                          b.hist_round, wl));
@@ -800,7 +801,7 @@ int run_tiled(thin_ctx* ctx, const thin_image* ims, const std::vector<int>& work
     // Work lists: round 0 visits every tile, later rounds the tiles queued
     // by the round before.
     if ((rc = ensure(ctx, ctx->wl_list, sizeof(int32_t) * 2 * (size_t)ntiles))) return rc;
-    if ((rc = ensure(ctx, ctx->wl_meta, sizeof(int32_t) * (4 + (size_t)ntiles)))) return rc;
+    if ((rc = ensure(ctx, ctx->wl_meta, sizeof(int32_t) * (12 + (size_t)ntiles)))) return rc;
 
     TiledBufs b{};
     b.imgs = static_cast<ImgDev*>(ctx->imgs.ptr);
@@ -1301,7 +1302,7 @@ int run_noalloc(thin_ctx* ctx, const thin_image& im, thin_stats* stats)
     const uint64_t o_bits = take(2 * ntiles * (uint64_t)thin::history_words(shape) * sizeof(uint32_t));
     const uint64_t o_hround = take(2 * ntiles * sizeof(int32_t));
     const uint64_t o_list = take(2 * ntiles * sizeof(int32_t));
-    const uint64_t o_meta = take((4 + ntiles) * sizeof(int32_t));
+    const uint64_t o_meta = take((12 + ntiles) * sizeof(int32_t));
     const uint64_t o_twin = take((uint64_t)im.h * (uint64_t)pitch_of(im) * bpp);
     if (off > thin::kNoAllocScratchBytes || ntiles > (uint64_t)INT_MAX / 2)
         return fail(ctx, THIN_ENOMEM,
