@@ -12,12 +12,13 @@
 //
 // Each of the four recursions of a pass (causal and anticausal, smoothing
 // and derivative) runs in its own thread, one thread per column (coalesced
-// across a wave) or per row, writing its own plane; the row pass adds the
-// two halves of its input as it reads them, and a last elementwise pass adds
-// the halves of gx and gy and stores the result.  Every product and sum is
-// rounded on its own, in the association order written below (no
-// contraction into fused multiply-adds), so the float32 result is
-// reproducible bit for bit.
+// across a wave; columns of up to 1024 samples split into segments, below)
+// or per row, writing its own plane; the row pass adds the two halves of
+// its input as it reads them, and a last elementwise pass adds the halves
+// of gx and gy and stores the result.  Every product and sum is rounded on
+// its own, in the association order written below (no contraction into
+// fused multiply-adds), so the float32 result is reproducible bit for bit
+// on a given image size.
 #include "thin_internal.h"
 
 #pragma clang fp contract(off)
@@ -162,6 +163,120 @@ __global__ __launch_bounds__(kGradThreads) void k_grad_rows(const float* __restr
     }
 }
 
+// Columns of at most kSegLen * kSegMax samples also run split into segments
+// of kSegLen samples, one wave per segment and 64 lines per block (one per
+// lane), so a short column's recursion is not one thread's chain of n
+// dependent steps.  Each recursion is linear in its output state: a
+// segment first runs from a zero state (the first segment from the edge's
+// steady state, which is its true state), then lane by lane wave 0 carries
+// the true state from segment to segment (the true final state of a full
+// segment is its zero-state final state plus E times its entering state, E
+// the 2 x 2 map of the homogeneous recursion over kSegLen steps), and each
+// segment adds z1[t] Y1 + z2[t] Y2 to its samples, z1 and z2 the homogeneous
+// responses to the entering state (Y1, Y2) = (y[start - 1], y[start - 2]).
+// The sums associate differently from the one-chain form, so the result
+// agrees with it to rounding (the tests compare both with float64), not bit
+// for bit.
+constexpr int kSegLen = 64;
+constexpr int kSegMax = 16;
+
+template <int KIND, typename Line>
+__device__ __forceinline__ void run_line_seg(const GradCoef& co, const Line& x, int n, bool live,
+                                             float* __restrict__ out, int64_t ostride, int seg,
+                                             int nseg, float2 (*s_state)[64], int lane)
+{
+    constexpr bool causal = KIND == 0 || KIND == 2;
+    constexpr bool smooth = KIND == 0 || KIND == 1;
+    auto at = [&](int p) { return causal ? p : n - 1 - p; };  // sample of processing position p
+    const int p0 = seg * kSegLen;
+    float y[kSegLen];
+    float s1 = 0.f, s2 = 0.f;
+    if (live && p0 < n) {
+        const float edge = x(at(0));
+        if (seg == 0) {
+            s1 = edge * (causal ? (smooth ? co.s_plus : co.d_plus) : (smooth ? co.s_minus : co.d_minus));
+            s2 = s1;
+        }
+        float x1 = p0 >= 1 ? x(at(p0 - 1)) : edge;
+        float x2 = p0 >= 2 ? x(at(p0 - 2)) : edge;
+#pragma unroll
+        for (int t = 0; t < kSegLen; ++t) {
+            if (p0 + t < n) {
+                const float xm = x(at(p0 + t));
+                if (causal) {
+                    y[t] = smooth ? smooth_causal(co, xm, x1, s1, s2) : deriv_causal(co, x1, s1, s2);
+                    x1 = xm;
+                } else {
+                    y[t] = smooth ? smooth_anti(co, x1, x2, s1, s2) : deriv_anti(co, x1, s1, s2);
+                    x2 = x1;
+                    x1 = xm;
+                }
+            }
+        }
+    }
+    s_state[seg][lane] = make_float2(s1, s2);  // zero-state final (y[last], y[last - 1])
+    __syncthreads();
+    if (seg == 0) {
+        // E from the homogeneous recursion z[t] = b1 z[t-1] + b2 z[t-2] over kSegLen steps
+        float a1 = 1.f, a2 = 0.f, c1 = 0.f, c2 = 1.f;  // (z[t-1], z[t-2]) of both bases
+        for (int t = 0; t < kSegLen; ++t) {
+            const float an = co.b1 * a1 + co.b2 * a2, cn = co.b1 * c1 + co.b2 * c2;
+            a2 = a1;
+            a1 = an;
+            c2 = c1;
+            c1 = cn;
+        }
+        float Y1 = s_state[0][lane].x, Y2 = s_state[0][lane].y;
+        for (int k = 1; k < nseg; ++k) {
+            const float2 loc = s_state[k][lane];
+            s_state[k][lane] = make_float2(Y1, Y2);
+            const float n1 = loc.x + (a1 * Y1 + c1 * Y2), n2 = loc.y + (a2 * Y1 + c2 * Y2);
+            Y1 = n1;
+            Y2 = n2;
+        }
+    }
+    __syncthreads();
+    if (!live || p0 >= n) return;
+    if (seg > 0) {
+        const float Y1 = s_state[seg][lane].x, Y2 = s_state[seg][lane].y;
+        float a1 = 1.f, a2 = 0.f, c1 = 0.f, c2 = 1.f;
+#pragma unroll
+        for (int t = 0; t < kSegLen; ++t) {
+            const float an = co.b1 * a1 + co.b2 * a2, cn = co.b1 * c1 + co.b2 * c2;
+            a2 = a1;
+            a1 = an;
+            c2 = c1;
+            c1 = cn;
+            y[t] = y[t] + (an * Y1 + cn * Y2);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kSegLen; ++t)
+        if (p0 + t < n) out[(int64_t)at(p0 + t) * ostride] = y[t];
+}
+
+// Column pass on segments: blockIdx.y picks the recursion, lane = column,
+// threadIdx.y = segment.
+template <typename T>
+__global__ __launch_bounds__(64 * kSegMax) void k_grad_cols_seg(const T* __restrict__ src,
+                                                                 int64_t pitch, int h, int w,
+                                                                 float* __restrict__ out,
+                                                                 int64_t plane, GradCoef co)
+{
+    __shared__ float2 s_state[kSegMax][64];
+    const int lane = threadIdx.x, seg = threadIdx.y, nseg = blockDim.y;
+    const int j = blockIdx.x * 64 + lane;
+    const bool live = j < w;
+    const ColLine<T> line{src + (live ? j : 0), pitch};
+    float* o = out + (int64_t)blockIdx.y * plane + (live ? j : 0);
+    switch (blockIdx.y) {
+    case 0: run_line_seg<0>(co, line, h, live, o, w, seg, nseg, s_state, lane); break;
+    case 1: run_line_seg<1>(co, line, h, live, o, w, seg, nseg, s_state, lane); break;
+    case 2: run_line_seg<2>(co, line, h, live, o, w, seg, nseg, s_state, lane); break;
+    default: run_line_seg<3>(co, line, h, live, o, w, seg, nseg, s_state, lane); break;
+    }
+}
+
 // gx = gx+ + gx-, gy = gy+ + gy-, magnitude, stored value; one thread per pixel.
 template <typename T>
 __global__ __launch_bounds__(256) void k_grad_out(const float* __restrict__ g, int h, int w,
@@ -192,14 +307,30 @@ hipError_t launch_gradient(hipStream_t stream, const void* src, int64_t src_pitc
     const dim3 block(kGradThreads);
     const dim3 gc((w + kGradThreads - 1) / kGradThreads, 4);
     const dim3 gr((h + kGradThreads - 1) / kGradThreads, 4);
-    if (src_dtype == 1)
+    // Segmented passes for lines of at most kSegLen * kSegMax samples (a
+    // pass has only 4 x (lines) chains, too few to fill the device); longer
+    // lines run one chain per thread.
+    const int seg_c = (h + kSegLen - 1) / kSegLen;
+    const dim3 sgc((w + 63) / 64, 4);
+    if (seg_c <= kSegMax) {
+        if (src_dtype == 1)
+            hipLaunchKernelGGL(k_grad_cols_seg<uint8_t>, sgc, dim3(64, seg_c), 0, stream,
+                               static_cast<const uint8_t*>(src), src_pitch, h, w, cols, plane, co);
+        else
+            hipLaunchKernelGGL(k_grad_cols_seg<uint16_t>, sgc, dim3(64, seg_c), 0, stream,
+                               static_cast<const uint16_t*>(src), src_pitch, h, w, cols, plane, co);
+    } else if (src_dtype == 1) {
         hipLaunchKernelGGL(k_grad_cols<uint8_t>, gc, block, 0, stream,
                            static_cast<const uint8_t*>(src), src_pitch, h, w, cols, plane, co);
-    else
+    } else {
         hipLaunchKernelGGL(k_grad_cols<uint16_t>, gc, block, 0, stream,
                            static_cast<const uint16_t*>(src), src_pitch, h, w, cols, plane, co);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // (The row pass stays one chain per row: its lanes walk different rows,
+    // and with segments eight times as many waves share each CU's cache
+    // for those scattered lines; measured 24 -> 50 us at 512 x 512.)
     hipLaunchKernelGGL(k_grad_rows, gr, block, 0, stream, cols, h, w, plane, rows, co);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const dim3 go((unsigned)((plane + 255) / 256));

@@ -82,7 +82,11 @@ def check(F, alpha, gain, out_dtype):
 
 CASES = [((1, 1), np.uint8), ((1, 9), np.uint8), ((9, 1), np.uint16), ((2, 2), np.uint8),
          ((3, 5), np.uint16), ((64, 80), np.uint8), ((200, 131), np.uint16), ((257, 300), np.uint8),
-         ((512, 512), np.uint8)]
+         ((512, 512), np.uint8),
+         # lines longer than the segmented passes take (1024 samples) run one
+         # chain per thread; 1024 itself is 16 full segments
+         ((1500, 40), np.uint8), ((30, 1300), np.uint16), ((1024, 65), np.uint8),
+         ((65, 1025), np.uint8)]
 
 
 @pytest.mark.parametrize("shape,dt", CASES, ids=lambda c: str(c))
