@@ -278,6 +278,36 @@ def test_graph_cache_tells_calls_apart():
                 assert_same(F, lam, 0, t.cpu().numpy(), st)
 
 
+def test_graph_mode_with_tile_queues_and_both_pixel_types():
+    """Graph replays of a call with per-round tile queues and one launch per
+    pixel type per round (each drawing its tiles from its own counter):
+    every image equals the same call without graphs, and a sample the
+    oracle."""
+    rng = np.random.default_rng(67)
+    Fs = []
+    for i in range(200):
+        h, w = (int(x) for x in rng.integers(150, 520, size=2))
+        Fs.append(synth.gen_blobs(h, w, 6700 + i, np.uint16 if i % 3 == 0 else np.uint8,
+                                  nblobs=10, sigma=(3.0, 14.0)))
+    lams = [int(x) for x in rng.choice([0, 5, 20, 50], size=len(Fs))]
+    adjs = [i % 2 for i in range(len(Fs))]
+    kw = dict(tile=64, steps_per_round=16, threads=256, variant=4)
+    say("case graph with tile queues")
+    plain = [torch.from_numpy(F.copy()).cuda() for F in Fs]
+    with thin.Context(**kw) as ctx:
+        ref_sts = ctx.run_batch(plain, lams, adjs)
+    with thin.Context(graph=True, **kw) as ctx:
+        for rep in range(2):  # the second call replays cached graphs
+            ts = [torch.from_numpy(F.copy()).cuda() for F in Fs]
+            sts = ctx.run_batch(ts, lams, adjs)
+            for i in range(len(Fs)):
+                assert torch.equal(ts[i], plain[i]), (rep, i)
+                assert (sts[i].passes, sts[i].lowerings) == (ref_sts[i].passes,
+                                                             ref_sts[i].lowerings), (rep, i)
+    for i in range(0, len(Fs), 25):
+        assert_same(Fs[i], lams[i], adjs[i], plain[i].cpu().numpy(), ref_sts[i])
+
+
 def test_autotune_leaves_inputs_and_results_unchanged():
     Fs = [synth.gen_blobs(80 + 40 * i, 120 + 30 * i, 500 + i, np.uint16 if i % 2 else np.uint8)
           for i in range(6)]
