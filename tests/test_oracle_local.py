@@ -59,7 +59,7 @@ def test_hand_worked_neighbourhoods(rec):
     assert pt.destructible == d
     assert pt.lambda_destructible == ld
     assert pt.alpha_minus == am
-    # The same verdict through the whole-image path (the C code reads the 3x3
+    # The same decision through the whole-image path (the C code reads the 3x3
     # from image coordinates itself): a 3x3 image has one interior pixel.
     n_ld, n_d = oracle.count_destructible(patch, lam, adj)
     assert (n_ld, n_d) == (int(ld), int(d))
