@@ -406,6 +406,48 @@ def test_work_lists_match_full_scans(shape, monkeypatch):
         assert_same(Fs[i], lams[i], adjs[i], batch[i].cpu().numpy(), sts[i])
 
 
+@pytest.mark.parametrize("mode", ["default", "queues"])
+@pytest.mark.parametrize("seed", [81, 82, 83])
+def test_random_mixed_batches(seed, mode):
+    """Random batches: both pixel types, both operators, random lambda and
+    pairing, some images as pitched views of wider buffers; every image
+    against the oracle.  "default": sides log-uniform in 3..1100 (a few
+    megapixels: the 128x128 bit-flag tiles, tiny and partial tiles next to
+    full ones); "queues": 180 images with sides in 40..700 on 64x64 bit-flag
+    tiles, enough tiles for per-round tile queues and the per-launch tile
+    counters."""
+    rng = np.random.default_rng(seed)
+    n, lo, hi = (90, 3, 1100) if mode == "default" else (180, 40, 700)
+    kw = {} if mode == "default" else dict(tile=64, steps_per_round=16, threads=512, variant=4)
+    Fs, ts, lams, adjs, ops = [], [], [], [], []
+    for i in range(n):
+        h, w = (int(round(np.exp(x))) for x in rng.uniform(np.log(lo), np.log(hi), size=2))
+        dt = np.uint16 if rng.random() < 0.3 else np.uint8
+        F = synth.gen_blobs(h, w, seed * 1000 + i, dt, nblobs=8, sigma=(2.0, 12.0))
+        lam = int(rng.choice([0, 3, 20, 60]))
+        if dt == np.uint16:
+            lam *= 257
+        Fs.append(F)
+        lams.append(lam)
+        adjs.append(int(rng.integers(0, 2)))
+        ops.append("skeleton" if rng.random() < 0.3 else "leveling")
+        if rng.random() < 0.3:
+            pad = int(rng.integers(1, 9))
+            big = torch.zeros((h, w + pad), dtype=torch.uint8 if dt == np.uint8 else torch.uint16,
+                              device="cuda")
+            big[:, :w] = torch.from_numpy(F.copy()).cuda()
+            ts.append(big[:, :w])
+        else:
+            ts.append(torch.from_numpy(F.copy()).cuda())
+    say("case random batch seed", seed, mode, "pixels", sum(F.size for F in Fs))
+    with thin.Context(**kw) as ctx:
+        sts = ctx.run_batch(ts, lams, adjs, ops=ops)
+    torch.cuda.synchronize()
+    for i in range(n):
+        ref = oracle.sweep_dirty(Fs[i], lams[i], adjs[i], op=ops[i])
+        assert_same(Fs[i], lams[i], adjs[i], ts[i].cpu().numpy(), sts[i], ref)
+
+
 def test_c_thin_run_entry_point():
     """thin_run itself (Context.run goes through thin_run_batch)."""
     F = synth.gen_blobs(97, 131, 4242, np.uint16, nblobs=8, sigma=(2.0, 9.0))
